@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q9 + MLS-IBM step on one MI355X.
+
+A step is one pass of the whole hot path: immersed-boundary force and
+spreading, the lattice pass (streaming, walls, forced collision) and the
+surface-stress / rigid-body update, for every channel of the workload.
+
+Default workload: the Re = 20 Couette channel (400 x 100 lattice, periodic
+in x, walls moving at -U/+U, one neutrally buoyant ellipse of aspect ratio 2
+and major axis 25 with 64 markers), FP32 storage.  Other workloads of the
+same family: --workload sedimentation | ensemble | large | adjoint.
+
+Prints one JSON line with the metric, a roofline object for the dominant
+kernel (HIP-event timing of that kernel alone on the library's stream) and a
+CPU baseline from the FP64 oracle run on a bounded sample of the workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS fused D2Q9+MLS-IBM step (plain vs batched/FP16); adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {0: 144, 1: 72, 2: 36}  # 9 reads + 9 writes per node
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
+DTYPE = {0: "f64", 1: "f32", 2: "f32 (f16 storage)"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="couette",
+                    choices=["couette", "sedimentation", "ensemble", "large", "adjoint"])
+    ap.add_argument("--storage", default=None, choices=list(STORAGE))
+    ap.add_argument("--plain", action="store_true",
+                    help="ensemble only: one handle per channel (per-channel launches)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 256 MiB (counter calibration)")
+    ap.add_argument("--tile-w", type=int, default=None)
+    ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--persistent", type=int, default=None)
+    ap.add_argument("--xcd-remap", type=int, default=None)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the lattice launch shape with the project autotuner first")
+    return ap.parse_args()
+
+
+def default_steps(name):
+    return {"couette": (50000, 2000), "sedimentation": (2000, 200), "ensemble": (1000, 100),
+            "large": (2000, 200), "adjoint": (2000, 200)}[name]
+
+
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle as it stands, one host thread, on the first channel of
+    the workload for as many steps as fit in about `seconds`."""
+    import oracle
+
+    cfg, parts = wl.channels[0]
+    cfg = dict(cfg, storage=0)
+    o = oracle.Oracle(cfg)
+    for p in parts:
+        o.add_particle(p)
+    nodes = cfg["nx"] * cfg["ny"]
+    t0 = time.perf_counter()
+    o.step(2, record=False)
+    per = (time.perf_counter() - t0) / 2
+    n = max(2, int(seconds / max(per, 1e-9)))
+    t0 = time.perf_counter()
+    o.step(n, record=False)
+    dt = time.perf_counter() - t0
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n} steps of channel 0 ({cfg['nx']}x{cfg['ny']}, {len(parts)} particle(s)) "
+                      f"in FP64 on one host thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1606_01805_amd import Solver
+    from workloads import configs as C
+
+    steps, warm = default_steps(args.workload)
+    steps = args.steps if args.steps is not None else steps
+    warm = args.warmup if args.warmup is not None else warm
+    storage = STORAGE[args.storage] if args.storage else (0 if args.workload == "sedimentation" else 1)
+    wl = C.BY_NAME[args.workload](storage=storage)
+    tuning = {}
+    if args.tile_w:
+        tuning["tile_w"] = args.tile_w
+    if args.rows:
+        tuning["rows_per_thread"] = args.rows
+    if args.persistent is not None:
+        tuning["persistent_wgs"] = args.persistent
+    if args.xcd_remap is not None:
+        tuning["xcd_remap"] = args.xcd_remap
+
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    solvers = ([Solver([ch], tuning=tuning) for ch in wl.channels] if args.plain
+               else [Solver(wl.channels, tuning=tuning)])
+    tune_report = None
+    if args.autotune:
+        from paper_1606_01805_amd.tune import autotune
+
+        best, res = autotune(solvers[0], cache=None)
+        for s in solvers[1:]:
+            s.set_tuning(**best)
+        tune_report = {k: v * 1e6 for k, v in res.items()}
+    for s in solvers:
+        s.step(warm, record=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps, record=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nodes = wl.nodes
+    mlups = nodes * steps / dt / 1e6
+
+    # Per-kernel device time, HIP events around back-to-back launches of each
+    # kernel alone on the library's stream (after the timed region).
+    s0 = solvers[0]
+    s0.checkpoint_save(7)
+    us = s0.time_kernels(args.kernel_reps)
+    s0.checkpoint_restore(7)
+    names = ["ibm_force", "lattice", "traction"]
+    k = int(max(range(3), key=lambda i: us[i]))
+    nodes0 = sum(c["nx"] * c["ny"] for c in s0.cfgs)
+    lattice_bytes = nodes0 * BYTES_PER_LUP[storage]
+    if k == 1:
+        ach = lattice_bytes / (us[1] * 1e-6) / 1e9
+        roof = {"kernel": "lattice_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": lattice_bytes, "us_per_launch": us[1]}
+    else:
+        # the immersed-boundary kernels are latency bound: one workgroup per
+        # particle; report the lattice kernel's bandwidth beside them
+        ach = lattice_bytes / (us[1] * 1e-6) / 1e9
+        roof = {"kernel": "lattice_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": lattice_bytes, "us_per_launch": us[1],
+                "dominant_by_time": names[k]}
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": dt / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[storage], "data": "synthetic",
+        "config": {"workload": wl.name, "nodes": nodes, "channels": len(wl.channels),
+                   "particles": wl.n_particles, "storage": ["F64", "F32", "F16S"][storage],
+                   "launch": "plain (per channel)" if args.plain else "single handle, HIP graph",
+                   "tuning": s0.tuning()},
+        "kernel_us": dict(zip(names, [float(v) for v in us])),
+        "roofline": roof,
+    }
+    if tune_report:
+        out["autotune_us_per_step"] = tune_report
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    for s in solvers:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the coupled
+ * lattice-Boltzmann / moving-least-squares immersed-boundary method of
+ * Coclite, de Tullio, Pascazio and Decuzzi ("A combined Lattice Boltzmann and
+ * Immersed Boundary approach for predicting the vascular transport of
+ * differently shaped particles", Computers and Fluids).
+ *
+ * One call to lbm_step advances every channel of a handle by whole time steps
+ * of the method (Sec. 1.2, last paragraph, and Sec. 1.3):
+ *   - D2Q9 BGK collision on the Hermite equilibrium with the Guo body-force
+ *     term (Sec. 1.1, Eqs. (2)-(7)), pull streaming (left-hand side of Eq. (4))
+ *     and Zou-He known-velocity walls (Sec. 1.1);
+ *   - MLS interpolation of the fluid velocity to the Lagrangian markers,
+ *     Lagrangian force and its spreading back to the lattice (Sec. 1.2,
+ *     Eqs. (8)-(12));
+ *   - surface-stress force and moment from normal probes (Sec. 1.3,
+ *     Eqs. (13), (14)) and the BDF2 rigid-body update (Eqs. (15), (16)).
+ * Lattice units throughout: dx = dt = 1, reference density 1, c_s^2 = 1/3,
+ * kinematic viscosity nu = (tau - 1/2)/3.
+ *
+ * Conventions
+ *   - All pointers passed to the library are HOST pointers unless stated.
+ *     `workspace` is a DEVICE pointer; `hip_stream` is a hipStream_t.
+ *   - Every entry point returns an lbm_status; none throws.  After a failure,
+ *     lbm_last_error(h) describes it (a handle-less failure of lbm_init is
+ *     described by lbm_last_error(NULL)).
+ *   - A handle is used from one host thread at a time.  All GPU work is
+ *     enqueued on the handle's stream.
+ *   - Lattice arrays exchanged with the host are row-major [ny][nx] in FP64;
+ *     population arrays are [9][ny][nx] in the velocity order of Eq. (3):
+ *     e0 = (0,0), e1 = (1,0), e2 = (0,1), e3 = (-1,0), e4 = (0,-1),
+ *     e5 = (1,1), e6 = (-1,1), e7 = (-1,-1), e8 = (1,-1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,    /* invalid argument or configuration */
+    LBM_ENOMEM = 2,    /* allocation failed or workspace too small */
+    LBM_EDEVICE = 3,   /* HIP runtime error */
+    LBM_ESTATE = 4,    /* call not allowed in the handle's current state */
+    LBM_ECAPACITY = 5, /* caller buffer or internal capacity too small */
+    LBM_EUNSTABLE = 6  /* non-finite or non-positive density detected */
+} lbm_status;
+
+enum { LBM_BC_PERIODIC = 0, LBM_BC_ZOUHE = 1 };
+enum { LBM_INIT_REST = 0, LBM_INIT_COUETTE = 1 };
+/* Population storage.  F64: FP64 populations, FP64 arithmetic.  F32: FP32
+ * storage of the deviation f_i - w_i, FP32 arithmetic.  F16S: FP16 storage of
+ * s_i (f_i - w_i) with s_i = 2^(fp16_exp + k_i), k_i = 1, 3, 5 for the rest,
+ * axis and diagonal directions, FP32 arithmetic.  In every form the
+ * immersed-boundary and rigid-body stages run in FP64. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
+enum { LBM_SIDE_XLO = 0, LBM_SIDE_XHI = 1, LBM_SIDE_YLO = 2, LBM_SIDE_YHI = 3 };
+/* Interpolation kernels of Sec. 2.2: exponential (Eq. (10)), cubic, quartic
+ * and cosine (Eqs. (17)-(19)). */
+enum { LBM_W_EXP = 0, LBM_W_CUBIC = 1, LBM_W_QUARTIC = 2, LBM_W_COSINE = 3 };
+/* c_l of Eq. (12): segment length (force conservation) or 1. */
+enum { LBM_SPREAD_SEGMENT = 0, LBM_SPREAD_UNIT = 1 };
+
+#define LBM_PSTATE 10 /* per particle: x, y, theta, u, v, omega, Fx, Fy, M, channel */
+
+/* One channel (an independent lattice).  Channels of one handle must share
+ * `storage`.  At most one axis may carry Zou-He walls (no corners). */
+typedef struct lbm_channel_config {
+    int32_t nx, ny;          /* lattice nodes, >= 3 each */
+    double tau;              /* BGK relaxation time, > 1/2 */
+    int32_t bc_x, bc_y;      /* LBM_BC_PERIODIC or LBM_BC_ZOUHE */
+    double u_wall[4][2];     /* wall velocities of sides x-, x+, y-, y+ */
+    int32_t init;            /* LBM_INIT_REST, or LBM_INIT_COUETTE (needs bc_y =
+                                ZOUHE): u_x linear in y between the y- and y+
+                                wall speeds (Sec. 3.1) */
+    double body_force[2];    /* uniform body force on the fluid */
+    double gravity[2];       /* gravity on the particles, applied as
+                                (1 - rho_f/rho_s) g */
+    int32_t storage;         /* LBM_STORE_* */
+    int32_t fp16_exp;        /* scale exponent K of the F16S form (0..14) */
+    double mls_rw;           /* MLS support size r_w (Sec. 1.2: 2.6) */
+    double mls_alpha;        /* exponential-kernel width (Eq. (10): 0.3) */
+    double probe_dn;         /* probe length along the normal (Sec. 1.3: 1.2) */
+    int32_t mls_kernel;      /* LBM_W_* */
+    int32_t spread_scale;    /* LBM_SPREAD_* */
+} lbm_channel_config;
+
+/* One rigid particle as a closed set of Lagrangian markers (Sec. 1.2): the
+ * markers sit on segment centres in the body frame (centroid at the origin);
+ * nrm are outward unit normals; ds the segment lengths S_l of Eqs. (12)-(14).
+ * Mass m = density_ratio * area and moment of inertia
+ * I = density_ratio * polar_moment (Eqs. (15), (16)). */
+typedef struct lbm_particle_desc {
+    double x, y, theta;      /* initial centroid and angle (theta rotates the
+                                body frame counter-clockwise) */
+    double u, v, omega;      /* initial linear and angular velocity */
+    double density_ratio;    /* rho_s / rho_f, > 0 */
+    double area;             /* body area, > 0 */
+    double polar_moment;     /* integral of |r|^2 over the body, > 0 */
+    int32_t n_markers;       /* >= 3 */
+    const double* xi;        /* [n_markers][2] */
+    const double* nrm;       /* [n_markers][2] */
+    const double* ds;        /* [n_markers] */
+} lbm_particle_desc;
+
+/* Launch and schedule choices of the lattice pass (see lbm_set_tuning). */
+typedef struct lbm_tuning {
+    int32_t tile_w;          /* nodes per tile along x: 64, 128 or 256 */
+    int32_t rows_per_thread; /* consecutive rows handled by one thread: 1, 2, 4 */
+    int32_t persistent_wgs;  /* 0: one workgroup per tile; > 0: that many
+                                workgroups striding over the tile table */
+    int32_t use_graph;       /* 1: replay lbm_step's steps from a HIP graph */
+    int32_t xcd_remap;       /* 1: hand each of the 8 XCDs (one L2 each) a
+                                contiguous block of tiles, so tiles that share
+                                halo cache lines run under the same L2 */
+} lbm_tuning;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Device bytes needed for the population buffers (two ping-pong buffers) of
+ * n_channels channels.  0 on invalid input. */
+size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n_channels);
+
+/* Create a handle for n_channels (>= 1) independent channels; n_channels > 1
+ * advances all of them by single launches per kernel phase (batched form).
+ * cfg: host array of n_channels configs, copied.  hip_stream: the stream all
+ * work is enqueued on (NULL = the null stream).  workspace: device memory of
+ * at least lbm_workspace_bytes(cfg, n) bytes, owned by the caller and kept
+ * alive until lbm_destroy; NULL makes the library allocate it.  The
+ * populations are initialised to the equilibrium of density 1 and the initial
+ * velocity (rest or Couette) and the walls are applied.
+ * Errors: LBM_EINVAL (bad field, tau <= 1/2, nx or ny < 3, two wall axes,
+ * mixed storage), LBM_ENOMEM (workspace_bytes too small), LBM_EDEVICE. */
+int lbm_init(const lbm_channel_config* cfg, int32_t n_channels, void* hip_stream,
+             void* workspace, size_t workspace_bytes, lbm_handle** out);
+
+/* Add a particle to `channel` before the first lbm_step.  The marker arrays
+ * are copied.  The history of the
+ * BDF2 scheme starts equal to the initial state.
+ * Errors: LBM_EINVAL (n_markers < 3, non-unit normal, non-finite or
+ * non-positive value, body closer than 3 nodes to a wall, body wider than
+ * the channel), LBM_ESTATE (after the first step), LBM_ECAPACITY (body too
+ * large for the per-particle force patch). */
+int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_particle_desc* d, int32_t* out_id);
+
+/* Advance every channel by n_steps (>= 0) time steps.  If traj is not NULL
+ * (host pointer) it receives [n_steps][n_particles][LBM_PSTATE]: the
+ * particle state at level n+1 and the force and moment of level n, for each
+ * step n, particles in the order they were added.  Returns after the work is
+ * complete.  Errors: LBM_EUNSTABLE (a density became non-positive or
+ * non-finite, or a particle state non-finite; the step is in lbm_last_error),
+ * LBM_ECAPACITY (a particle outgrew its force patch), LBM_EDEVICE. */
+int lbm_step(lbm_handle* h, int32_t n_steps, double* traj);
+
+/* Current state of all particles: out[n][LBM_PSTATE] (host), the last step's
+ * force and moment included.  *n_out receives the particle count even when
+ * cap is too small (then LBM_ECAPACITY). */
+int lbm_get_particles(const lbm_handle* h, double* out, int32_t cap, int32_t* n_out);
+
+/* Density and velocity (sum f e + g/2)/rho of the current populations of a
+ * channel, each [ny][nx] (host); any pointer may be NULL. */
+int lbm_get_fields(lbm_handle* h, int32_t channel, double* rho, double* ux, double* uy);
+
+/* Current populations f^n (after streaming and walls) of a channel, converted
+ * to FP64, [9][ny][nx] (host). */
+int lbm_get_populations(lbm_handle* h, int32_t channel, double* f);
+
+/* Replace the current populations of a channel by f [9][ny][nx] (host, FP64),
+ * rounded to the channel's storage form.  The values must already satisfy the
+ * wall conditions they are meant to (walls are applied from the next step). */
+int lbm_set_populations(lbm_handle* h, int32_t channel, const double* f);
+
+/* Save / restore the complete state (populations, particles, step counter) in
+ * slot 0..7; slots are allocated on first use.  Restoring a slot saved with a
+ * different particle set is LBM_ESTATE. */
+int lbm_checkpoint_save(lbm_handle* h, int32_t slot);
+int lbm_checkpoint_restore(lbm_handle* h, int32_t slot);
+
+/* Lattice-pass launch choices; takes effect at the next lbm_step. */
+int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
+int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
+
+/* Average device time per launch, in microseconds, of the three kernels of a
+ * step (out_us[0] = immersed-boundary force and spreading, [1] = lattice pass,
+ * [2] = surface stress and rigid-body update), measured with HIP events on the
+ * handle's stream over `reps` back-to-back launches of each kernel alone.  The
+ * launches run real steps, so the state advances by reps steps per kernel
+ * phase; use a checkpoint around the call to keep it. */
+int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]);
+
+/* Total steps taken by the handle. */
+int64_t lbm_steps_done(const lbm_handle* h);
+
+/* Text of the last failure on h (or of the last handle-less failure when h is
+ * NULL).  Owned by the library; valid until the next call on h. */
+const char* lbm_last_error(const lbm_handle* h);
+
+/* Free the handle and everything the library allocated (not a caller
+ * workspace).  NULL is accepted. */
+int lbm_destroy(lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

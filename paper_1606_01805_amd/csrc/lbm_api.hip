@@ -1,0 +1,713 @@
+// Host side of the C ABI declared in include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbmk;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct PartHost {
+    lbm_particle_desc d;
+    std::vector<double> xi, nrm, ds;
+    int chan;
+    double rb;
+    int cap;
+};
+
+struct Checkpoint {
+    void* f = nullptr;
+    PartDev* p = nullptr;
+    long long* step = nullptr;
+    long long steps = 0;
+    int cur = 0;
+    int nparts = -1;
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct lbm_handle {
+    std::vector<lbm_channel_config> cfg;
+    int store = 0;
+    size_t elem = 8;
+    hipStream_t stream = nullptr;
+    void* buf[2] = {nullptr, nullptr};
+    void* ws_alloc = nullptr;
+    size_t buf_bytes = 0;
+    std::vector<ChanDev> hchan;
+    ChanDev* dchan = nullptr;
+    std::vector<TileDev> htiles;
+    TileDev* dtiles = nullptr;
+    lbm_tuning tune{256, 1, 0, 1, 1};
+    bool tiles_dirty = true;
+    std::vector<PartHost> parts;
+    std::vector<int> dev_of_user;  // user particle id -> device index
+    std::vector<int> user_of_dev;
+    PartDev* dparts = nullptr;
+    double2* dxi = nullptr;
+    double2* dnrm = nullptr;
+    double* dds = nullptr;
+    double2* dpatch = nullptr;
+    double2* dcontrib = nullptr;
+    double* dmscr = nullptr;
+    int* dflags = nullptr;
+    int* dtflag = nullptr;
+    long long* dstep = nullptr;
+    double* drec = nullptr;
+    int nparts = 0;
+    int max_cells = kMaxCellsDefault;
+    int cur = 0;
+    long long steps = 0;
+    bool finalized = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    Checkpoint ck[8];
+    std::string err;
+};
+
+#define FAIL(h, code, ...)                                                       \
+    do {                                                                         \
+        char _b[512];                                                            \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                                   \
+        if (h) (h)->err = _b; else g_err = _b;                                   \
+        return code;                                                             \
+    } while (0)
+
+#define HIPCHK(h, expr)                                                          \
+    do {                                                                         \
+        hipError_t _e = (expr);                                                  \
+        if (_e != hipSuccess)                                                    \
+            FAIL(h, LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+static bool finite_all(const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+static int validate_cfg(const lbm_channel_config& c, int idx) {
+    auto bad = [&](const char* what) {
+        char b[256];
+        snprintf(b, sizeof(b), "channel %d: %s", idx, what);
+        g_err = b;
+        return LBM_EINVAL;
+    };
+    if (c.nx < 3 || c.ny < 3) return bad("nx and ny must be >= 3");
+    if ((long long)c.nx * c.ny > (1LL << 31) / 16) return bad("lattice too large");
+    if (!std::isfinite(c.tau) || !(c.tau > 0.5)) return bad("tau must be finite and > 1/2");
+    if ((c.bc_x != LBM_BC_PERIODIC && c.bc_x != LBM_BC_ZOUHE) ||
+        (c.bc_y != LBM_BC_PERIODIC && c.bc_y != LBM_BC_ZOUHE))
+        return bad("bad boundary kind");
+    if (c.bc_x == LBM_BC_ZOUHE && c.bc_y == LBM_BC_ZOUHE) return bad("walls on both axes (corners) are not supported");
+    if (c.init != LBM_INIT_REST && c.init != LBM_INIT_COUETTE) return bad("bad init");
+    if (c.init == LBM_INIT_COUETTE && c.bc_y != LBM_BC_ZOUHE) return bad("Couette start needs walls on y");
+    if (c.storage < LBM_STORE_F64 || c.storage > LBM_STORE_F16S) return bad("bad storage");
+    if (c.fp16_exp < 0 || c.fp16_exp > 14) return bad("fp16_exp must be in 0..14");
+    if (!finite_all(&c.u_wall[0][0], 8) || !finite_all(c.body_force, 2) || !finite_all(c.gravity, 2))
+        return bad("non-finite wall speed, body force or gravity");
+    for (int s = 0; s < 4; ++s)
+        if (std::fabs(c.u_wall[s][0]) >= 1.0 || std::fabs(c.u_wall[s][1]) >= 1.0)
+            return bad("wall speed must be below 1 lattice unit");
+    if (!std::isfinite(c.mls_rw) || !(c.mls_rw > 2.13)) return bad("mls_rw must exceed the 3x3 stencil radius 1.5*sqrt(2)");
+    if (!std::isfinite(c.mls_alpha) || !(c.mls_alpha > 0)) return bad("mls_alpha must be > 0");
+    if (!std::isfinite(c.probe_dn) || c.probe_dn < 0) return bad("probe_dn must be >= 0");
+    if (c.mls_kernel < LBM_W_EXP || c.mls_kernel > LBM_W_COSINE) return bad("bad mls_kernel");
+    if (c.spread_scale != LBM_SPREAD_SEGMENT && c.spread_scale != LBM_SPREAD_UNIT) return bad("bad spread_scale");
+    return LBM_OK;
+}
+
+static size_t pitch_of(int nx) { return round_up((size_t)nx, 64); }
+
+static size_t buffer_bytes(const lbm_channel_config* cfg, int n, size_t elem) {
+    size_t e = 0;
+    for (int i = 0; i < n; ++i) e += 9 * (size_t)cfg[i].ny * pitch_of(cfg[i].nx);
+    return round_up(e * elem, 4096);
+}
+
+static size_t elem_size(int store) { return store == LBM_STORE_F64 ? 8 : (store == LBM_STORE_F32 ? 4 : 2); }
+
+extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) {
+    if (!cfg || n < 1) return 0;
+    for (int i = 0; i < n; ++i)
+        if (validate_cfg(cfg[i], i) != LBM_OK || cfg[i].storage != cfg[0].storage) return 0;
+    return 2 * buffer_bytes(cfg, n, elem_size(cfg[0].storage));
+}
+
+static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
+    StepArgs a{};
+    a.parity = parity < 0 ? cur : parity;
+    a.tflag = h->dtflag;
+    a.tile_w = h->tune.tile_w;
+    a.tile_h = (256 / h->tune.tile_w) * h->tune.rows_per_thread;
+    a.fin = h->buf[cur];
+    a.fout = h->buf[1 - cur];
+    a.chan = h->dchan;
+    a.nchan = (int)h->cfg.size();
+    a.tiles = h->dtiles;
+    a.ntiles = (int)h->htiles.size();
+    a.parts = h->dparts;
+    a.nparts = h->nparts;
+    a.persistent = h->tune.persistent_wgs;
+    a.xcd_remap = h->tune.xcd_remap;
+    a.xi = h->dxi;
+    a.nrm = h->dnrm;
+    a.ds = h->dds;
+    a.patch = h->dpatch;
+    a.contrib = h->dcontrib;
+    a.mscr = h->dmscr;
+    a.flags = h->dflags;
+    a.dstep = h->dstep;
+    a.rec = h->drec;
+    a.max_cells = h->max_cells;
+    return a;
+}
+
+static void drop_graphs(lbm_handle* h) {
+    for (int i = 0; i < 2; ++i)
+        if (h->gexec[i]) {
+            (void)hipGraphExecDestroy(h->gexec[i]);
+            h->gexec[i] = nullptr;
+        }
+}
+
+static int build_tiles(lbm_handle* h) {
+    const int tw = h->tune.tile_w, th = (256 / tw) * h->tune.rows_per_thread;
+    h->htiles.clear();
+    for (int c = 0; c < (int)h->cfg.size(); ++c) {
+        h->hchan[c].tile0 = (int)h->htiles.size();
+        h->hchan[c].tiles_x = (h->cfg[c].nx + tw - 1) / tw;
+        for (int y0 = 0; y0 < h->cfg[c].ny; y0 += th)
+            for (int x0 = 0; x0 < h->cfg[c].nx; x0 += tw) h->htiles.push_back(TileDev{c, x0, y0, 0});
+    }
+    if (h->dtiles) (void)hipFree(h->dtiles);
+    if (h->dtflag) (void)hipFree(h->dtflag);
+    h->dtiles = nullptr;
+    h->dtflag = nullptr;
+    const size_t nt = h->htiles.size();
+    HIPCHK(h, hipMalloc(&h->dtiles, sizeof(TileDev) * nt));
+    HIPCHK(h, hipMemcpy(h->dtiles, h->htiles.data(), sizeof(TileDev) * nt, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMalloc(&h->dtflag, sizeof(int) * 2 * nt));
+    HIPCHK(h, hipMemset(h->dtflag, 0, sizeof(int) * 2 * nt));
+    HIPCHK(h, hipMemcpy(h->dchan, h->hchan.data(), sizeof(ChanDev) * h->hchan.size(), hipMemcpyHostToDevice));
+    h->tiles_dirty = false;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+static void fill_chan(ChanDev& d, const lbm_channel_config& c, long long off) {
+    memset(&d, 0, sizeof(d));
+    d.nx = c.nx;
+    d.ny = c.ny;
+    d.pitch = (int)pitch_of(c.nx);
+    d.bcx = c.bc_x;
+    d.bcy = c.bc_y;
+    d.kernel = c.mls_kernel;
+    d.spread_unit = c.spread_scale == LBM_SPREAD_UNIT;
+    d.off = off;
+    d.plane = (long long)c.ny * d.pitch;
+    d.tau = c.tau;
+    d.nu = (c.tau - 0.5) / 3.0;
+    for (int s = 0; s < 4; ++s)
+        for (int k = 0; k < 2; ++k) {
+            d.uw[s][k] = c.u_wall[s][k];
+            d.f_uw[s][k] = (float)c.u_wall[s][k];
+        }
+    for (int k = 0; k < 2; ++k) {
+        d.g[k] = c.body_force[k];
+        d.grav[k] = c.gravity[k];
+        d.f_g[k] = (float)c.body_force[k];
+    }
+    d.rw = c.mls_rw;
+    d.alpha = c.mls_alpha;
+    d.dn = c.probe_dn;
+    d.f_omega = (float)(1.0 / c.tau);
+    d.f_pref = (float)(1.0 - 1.0 / (2.0 * c.tau));
+    const int kk[3] = {1, 3, 5};
+    for (int k = 0; k < 3; ++k) {
+        d.sc[k] = std::ldexp(1.0f, c.fp16_exp + kk[k]);
+        d.isc[k] = std::ldexp(1.0f, -(c.fp16_exp + kk[k]));
+    }
+}
+
+extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, void* workspace,
+                        size_t workspace_bytes, lbm_handle** out) {
+    if (!out) FAIL((lbm_handle*)nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg || n < 1) FAIL((lbm_handle*)nullptr, LBM_EINVAL, "need at least one channel config");
+    for (int i = 0; i < n; ++i) {
+        int r = validate_cfg(cfg[i], i);
+        if (r) return r;
+        if (cfg[i].storage != cfg[0].storage)
+            FAIL((lbm_handle*)nullptr, LBM_EINVAL, "all channels of a handle must share the storage form");
+    }
+    lbm_handle* h = new (std::nothrow) lbm_handle();
+    if (!h) FAIL((lbm_handle*)nullptr, LBM_ENOMEM, "out of host memory");
+    h->cfg.assign(cfg, cfg + n);
+    h->store = cfg[0].storage;
+    h->elem = elem_size(h->store);
+    h->stream = (hipStream_t)stream;
+    h->buf_bytes = buffer_bytes(cfg, n, h->elem);
+    const size_t need = 2 * h->buf_bytes;
+    auto fail_init = [&](int code) {
+        g_err = h->err;
+        lbm_destroy(h);
+        return code;
+    };
+    if (workspace) {
+        if (workspace_bytes < need) {
+            char b[200];
+            snprintf(b, sizeof(b), "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+            h->err = b;
+            return fail_init(LBM_ENOMEM);
+        }
+        h->buf[0] = workspace;
+    } else {
+        if (hipMalloc(&h->ws_alloc, need) != hipSuccess) {
+            h->err = "hipMalloc of the population buffers failed";
+            return fail_init(LBM_ENOMEM);
+        }
+        h->buf[0] = h->ws_alloc;
+    }
+    h->buf[1] = (char*)h->buf[0] + h->buf_bytes;
+    {
+        // Force-patch capacity: the spreading kernel keeps one 64-bit marker
+        // mask per patch cell in LDS next to its static buffers.
+        int dev = 0, maxsh = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+            long long avail = (long long)maxsh - (long long)ibm_static_lds_bytes() - (long long)ibm_lds_bytes(0) - 1024;
+            h->max_cells = (int)std::max(1024LL, std::min(32768LL, avail / 8));
+        }
+    }
+    long long off = 0;
+    h->hchan.resize(n);
+    for (int i = 0; i < n; ++i) {
+        fill_chan(h->hchan[i], cfg[i], off);
+        off += 9LL * cfg[i].ny * (long long)pitch_of(cfg[i].nx);
+    }
+    int r;
+    if (hipMalloc(&h->dchan, sizeof(ChanDev) * n) != hipSuccess ||
+        hipMalloc(&h->dflags, sizeof(int) * 4) != hipSuccess ||
+        hipMalloc(&h->dstep, sizeof(long long)) != hipSuccess) {
+        h->err = "hipMalloc of handle state failed";
+        return fail_init(LBM_ENOMEM);
+    }
+    if (hipMemcpy(h->dchan, h->hchan.data(), sizeof(ChanDev) * n, hipMemcpyHostToDevice) != hipSuccess) {
+        h->err = "upload of channel table failed";
+        return fail_init(LBM_EDEVICE);
+    }
+    int fl[4] = {0, INT_MAX, 0, 0};
+    long long z = 0;
+    if (hipMemcpy(h->dflags, fl, sizeof(fl), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->dstep, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
+        h->err = "upload of flags failed";
+        return fail_init(LBM_EDEVICE);
+    }
+    if ((r = build_tiles(h)) != LBM_OK) return fail_init(r);
+    StepArgs a = make_args(h, 1);  // fout = buf[0]
+    for (int c = 0; c < n; ++c) {
+        hipError_t e = launch_init(h->store, a, c, cfg[c].init, cfg[c].nx, cfg[c].ny, h->stream);
+        if (e != hipSuccess) {
+            h->err = std::string("init kernel: ") + hipGetErrorString(e);
+            return fail_init(LBM_EDEVICE);
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        h->err = "init synchronisation failed";
+        return fail_init(LBM_EDEVICE);
+    }
+    h->cur = 0;
+    *out = h;
+    return LBM_OK;
+}
+
+extern "C" int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_particle_desc* d, int32_t* out_id) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (h->finalized) FAIL(h, LBM_ESTATE, "particles can only be added before the first step");
+    if (!d || channel < 0 || channel >= (int)h->cfg.size()) FAIL(h, LBM_EINVAL, "bad channel or descriptor");
+    const int n = d->n_markers;
+    if (n < 3 || n > 1024) FAIL(h, LBM_EINVAL, "n_markers must be in 3..1024");
+    if (!d->xi || !d->nrm || !d->ds) FAIL(h, LBM_EINVAL, "marker arrays must not be NULL");
+    double sc[9] = {d->x, d->y, d->theta, d->u, d->v, d->omega, d->density_ratio, d->area, d->polar_moment};
+    if (!finite_all(sc, 9) || !finite_all(d->xi, 2 * (size_t)n) || !finite_all(d->nrm, 2 * (size_t)n) ||
+        !finite_all(d->ds, n))
+        FAIL(h, LBM_EINVAL, "non-finite particle value");
+    if (!(d->density_ratio > 0) || !(d->area > 0) || !(d->polar_moment > 0))
+        FAIL(h, LBM_EINVAL, "density_ratio, area and polar_moment must be > 0");
+    double rb = 0;
+    for (int l = 0; l < n; ++l) {
+        double nn = d->nrm[2 * l] * d->nrm[2 * l] + d->nrm[2 * l + 1] * d->nrm[2 * l + 1];
+        if (std::fabs(nn - 1.0) > 1e-6) FAIL(h, LBM_EINVAL, "marker %d: normal is not a unit vector", l);
+        if (!(d->ds[l] > 0)) FAIL(h, LBM_EINVAL, "marker %d: ds must be > 0", l);
+        rb = std::max(rb, std::sqrt(d->xi[2 * l] * d->xi[2 * l] + d->xi[2 * l + 1] * d->xi[2 * l + 1]));
+    }
+    const lbm_channel_config& c = h->cfg[channel];
+    const double reach = rb + 3.0;
+    if (c.bc_y == LBM_BC_ZOUHE && (d->y - reach < 0 || d->y + reach > c.ny - 1))
+        FAIL(h, LBM_EINVAL, "particle closer than 3 nodes to a wall");
+    if (c.bc_x == LBM_BC_ZOUHE && (d->x - reach < 0 || d->x + reach > c.nx - 1))
+        FAIL(h, LBM_EINVAL, "particle closer than 3 nodes to a wall");
+    if (c.bc_y == LBM_BC_PERIODIC && (d->y < -1e6 || d->y > 1e6)) FAIL(h, LBM_EINVAL, "position out of range");
+    if (c.bc_x == LBM_BC_PERIODIC && (d->x < -1e6 || d->x > 1e6)) FAIL(h, LBM_EINVAL, "position out of range");
+    const int side = (int)std::ceil(2.0 * rb) + 6;
+    if (side > c.nx || side > c.ny) FAIL(h, LBM_EINVAL, "particle wider than the channel");
+    if ((long long)side * side > h->max_cells)
+        FAIL(h, LBM_ECAPACITY, "particle too large for the force patch (%d cells > %d)", side * side, h->max_cells);
+    PartHost p;
+    p.d = *d;
+    p.xi.assign(d->xi, d->xi + 2 * n);
+    p.nrm.assign(d->nrm, d->nrm + 2 * n);
+    p.ds.assign(d->ds, d->ds + n);
+    p.chan = channel;
+    p.rb = rb;
+    p.cap = side * side;
+    h->parts.push_back(std::move(p));
+    if (out_id) *out_id = (int)h->parts.size() - 1;
+    return LBM_OK;
+}
+
+static int finalize(lbm_handle* h) {
+    if (h->finalized) return LBM_OK;
+    const int np = (int)h->parts.size();
+    std::vector<int> order(np);
+    for (int i = 0; i < np; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->parts[a].chan < h->parts[b].chan; });
+    h->dev_of_user.assign(np, 0);
+    h->user_of_dev = order;
+    std::vector<PartDev> pd(np);
+    std::vector<double2> xi, nrm;
+    std::vector<double> ds;
+    long long cells = 0;
+    for (auto& ch : h->hchan) ch.p_begin = ch.p_end = 0;
+    for (int k = 0; k < np; ++k) {
+        const PartHost& P = h->parts[order[k]];
+        h->dev_of_user[order[k]] = k;
+        PartDev& q = pd[k];
+        memset(&q, 0, sizeof(q));
+        q.X[0] = q.Xm[0] = P.d.x;
+        q.X[1] = q.Xm[1] = P.d.y;
+        q.th = q.thm = P.d.theta;
+        q.V[0] = q.Vm[0] = P.d.u;
+        q.V[1] = q.Vm[1] = P.d.v;
+        q.Om = q.Omm = P.d.omega;
+        q.ratio = P.d.density_ratio;
+        q.m = P.d.density_ratio * P.d.area;
+        q.I = P.d.density_ratio * P.d.polar_moment;
+        q.chan = P.chan;
+        q.mbeg = (int)ds.size();
+        q.nm = P.d.n_markers;
+        q.patch_cap = P.cap;
+        q.patch_off = cells;
+        cells += P.cap;
+        for (int l = 0; l < q.nm; ++l) {
+            xi.push_back(make_double2(P.xi[2 * l], P.xi[2 * l + 1]));
+            nrm.push_back(make_double2(P.nrm[2 * l], P.nrm[2 * l + 1]));
+            ds.push_back(P.ds[l]);
+        }
+        ChanDev& ch = h->hchan[P.chan];
+        if (ch.p_end == ch.p_begin) ch.p_begin = k;
+        ch.p_end = k + 1;
+    }
+    h->nparts = np;
+    const size_t nmk = std::max<size_t>(ds.size(), 1);
+    HIPCHK(h, hipMalloc(&h->dparts, sizeof(PartDev) * std::max(np, 1)));
+    HIPCHK(h, hipMalloc(&h->dxi, sizeof(double2) * nmk));
+    HIPCHK(h, hipMalloc(&h->dnrm, sizeof(double2) * nmk));
+    HIPCHK(h, hipMalloc(&h->dds, sizeof(double) * nmk));
+    HIPCHK(h, hipMalloc(&h->dpatch, sizeof(double2) * std::max<long long>(cells, 1)));
+    HIPCHK(h, hipMalloc(&h->dcontrib, sizeof(double2) * 9 * nmk));
+    HIPCHK(h, hipMalloc(&h->dmscr, sizeof(double) * 4 * nmk));
+    HIPCHK(h, hipMalloc(&h->drec, sizeof(double) * 10 * kRecSlots * std::max(np, 1)));
+    if (np) {
+        HIPCHK(h, hipMemcpy(h->dparts, pd.data(), sizeof(PartDev) * np, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->dxi, xi.data(), sizeof(double2) * xi.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->dnrm, nrm.data(), sizeof(double2) * nrm.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->dds, ds.data(), sizeof(double) * ds.size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(h, hipMemset(h->dpatch, 0, sizeof(double2) * std::max<long long>(cells, 1)));
+    HIPCHK(h, hipMemcpy(h->dchan, h->hchan.data(), sizeof(ChanDev) * h->hchan.size(), hipMemcpyHostToDevice));
+    h->finalized = true;
+    return LBM_OK;
+}
+
+static int enqueue_step(lbm_handle* h, int cur) {
+    StepArgs a = make_args(h, cur);
+    HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+    HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+    HIPCHK(h, launch_traction(h->store, a, h->stream));
+    return LBM_OK;
+}
+
+static int run_steps(lbm_handle* h, long long n) {
+    const bool graph = h->tune.use_graph && h->stream != nullptr;
+    while (n > 0) {
+        if (graph && n >= 2) {
+            const int par = h->cur;
+            if (!h->gexec[par]) {
+                hipGraph_t g = nullptr;
+                HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+                int r1 = enqueue_step(h, par);
+                int r2 = r1 == LBM_OK ? enqueue_step(h, 1 - par) : r1;
+                hipError_t e = hipStreamEndCapture(h->stream, &g);
+                if (r2 != LBM_OK) return r2;
+                HIPCHK(h, e);
+                hipError_t ei = hipGraphInstantiate(&h->gexec[par], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                HIPCHK(h, ei);
+            }
+            const long long reps = n / 2;
+            for (long long r = 0; r < reps; ++r) HIPCHK(h, hipGraphLaunch(h->gexec[par], h->stream));
+            h->steps += 2 * reps;
+            n -= 2 * reps;
+        } else {
+            int r = enqueue_step(h, h->cur);
+            if (r) return r;
+            h->cur = 1 - h->cur;
+            h->steps += 1;
+            n -= 1;
+        }
+    }
+    return LBM_OK;
+}
+
+static int check_flags(lbm_handle* h) {
+    int fl[4];
+    HIPCHK(h, hipMemcpyAsync(fl, h->dflags, sizeof(fl), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (fl[2]) FAIL(h, LBM_ECAPACITY, "a particle outgrew its force patch");
+    if (fl[0])
+        FAIL(h, LBM_EUNSTABLE, "non-finite or non-positive density or particle state in step %d (counting from 1)",
+             fl[1] + 1);
+    return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_handle* h, int32_t n, double* traj) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (n < 0) FAIL(h, LBM_EINVAL, "n_steps must be >= 0");
+    int r;
+    if ((r = finalize(h)) != LBM_OK) return r;
+    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
+    if (!traj || h->nparts == 0) {
+        if ((r = run_steps(h, n)) != LBM_OK) return r;
+        return check_flags(h);
+    }
+    std::vector<double> rec((size_t)kRecSlots * h->nparts * 10);
+    long long done = 0;
+    while (done < n) {
+        const long long chunk = std::min<long long>(kRecSlots, n - done);
+        const long long s0 = h->steps;
+        if ((r = run_steps(h, chunk)) != LBM_OK) return r;
+        HIPCHK(h, hipMemcpyAsync(rec.data(), h->drec, sizeof(double) * rec.size(), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (long long j = 0; j < chunk; ++j) {
+            const long long slot = (s0 + j) % kRecSlots;
+            for (int u = 0; u < h->nparts; ++u) {
+                const int k = h->dev_of_user[u];
+                memcpy(traj + ((done + j) * h->nparts + u) * 10, &rec[(slot * h->nparts + k) * 10], 10 * sizeof(double));
+            }
+        }
+        done += chunk;
+    }
+    return check_flags(h);
+}
+
+extern "C" int lbm_get_particles(const lbm_handle* hc, double* out, int32_t cap, int32_t* n_out) {
+    lbm_handle* h = const_cast<lbm_handle*>(hc);
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    const int np = (int)h->parts.size();
+    if (n_out) *n_out = np;
+    if (cap < np) FAIL(h, LBM_ECAPACITY, "output holds %d particles, %d needed", cap, np);
+    if (np == 0) return LBM_OK;
+    if (!out) FAIL(h, LBM_EINVAL, "out is NULL");
+    if (!h->finalized) {
+        for (int u = 0; u < np; ++u) {
+            const lbm_particle_desc& d = h->parts[u].d;
+            double v[10] = {d.x, d.y, d.theta, d.u, d.v, d.omega, 0, 0, 0, (double)h->parts[u].chan};
+            memcpy(out + 10 * u, v, sizeof(v));
+        }
+        return LBM_OK;
+    }
+    std::vector<PartDev> pd(np);
+    HIPCHK(h, hipMemcpyAsync(pd.data(), h->dparts, sizeof(PartDev) * np, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int u = 0; u < np; ++u) {
+        const PartDev& q = pd[h->dev_of_user[u]];
+        double v[10] = {q.X[0], q.X[1], q.th, q.V[0], q.V[1], q.Om, q.F[0], q.F[1], q.M, (double)q.chan};
+        memcpy(out + 10 * u, v, sizeof(v));
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_populations(lbm_handle* h, int32_t ch, double* f) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (ch < 0 || ch >= (int)h->cfg.size() || !f) FAIL(h, LBM_EINVAL, "bad channel or NULL output");
+    int r;
+    if ((r = finalize(h)) != LBM_OK) return r;
+    const size_t n = (size_t)h->cfg[ch].nx * h->cfg[ch].ny;
+    double* d = nullptr;
+    HIPCHK(h, hipMalloc(&d, sizeof(double) * 9 * n));
+    StepArgs a = make_args(h, h->cur);
+    hipError_t e = launch_fields(h->store, a, ch, h->cfg[ch].nx, h->cfg[ch].ny, d, nullptr, nullptr, nullptr, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    HIPCHK(h, e);
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_fields(lbm_handle* h, int32_t ch, double* rho, double* ux, double* uy) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (ch < 0 || ch >= (int)h->cfg.size()) FAIL(h, LBM_EINVAL, "bad channel");
+    int r;
+    if ((r = finalize(h)) != LBM_OK) return r;
+    const size_t n = (size_t)h->cfg[ch].nx * h->cfg[ch].ny;
+    double* d = nullptr;
+    HIPCHK(h, hipMalloc(&d, sizeof(double) * 3 * n));
+    StepArgs a = make_args(h, h->cur);
+    hipError_t e = launch_fields(h->store, a, ch, h->cfg[ch].nx, h->cfg[ch].ny, nullptr, d, d + n, d + 2 * n, h->stream);
+    double* outs[3] = {rho, ux, uy};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        if (outs[k]) e = hipMemcpyAsync(outs[k], d + k * n, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    HIPCHK(h, e);
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_populations(lbm_handle* h, int32_t ch, const double* f) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (ch < 0 || ch >= (int)h->cfg.size() || !f) FAIL(h, LBM_EINVAL, "bad channel or NULL input");
+    const size_t n = (size_t)h->cfg[ch].nx * h->cfg[ch].ny;
+    if (!finite_all(f, 9 * n)) FAIL(h, LBM_EINVAL, "non-finite population");
+    double* d = nullptr;
+    HIPCHK(h, hipMalloc(&d, sizeof(double) * 9 * n));
+    hipError_t e = hipMemcpyAsync(d, f, sizeof(double) * 9 * n, hipMemcpyHostToDevice, h->stream);
+    StepArgs a = make_args(h, 1 - h->cur);  // fout = buf[cur]
+    if (e == hipSuccess) e = launch_set_pop(h->store, a, ch, h->cfg[ch].nx, h->cfg[ch].ny, d, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    HIPCHK(h, e);
+    return LBM_OK;
+}
+
+extern "C" int lbm_checkpoint_save(lbm_handle* h, int32_t slot) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (slot < 0 || slot >= 8) FAIL(h, LBM_EINVAL, "slot must be in 0..7");
+    int r;
+    if ((r = finalize(h)) != LBM_OK) return r;
+    Checkpoint& c = h->ck[slot];
+    if (!c.f) HIPCHK(h, hipMalloc(&c.f, h->buf_bytes));
+    if (!c.p) HIPCHK(h, hipMalloc(&c.p, sizeof(PartDev) * std::max(h->nparts, 1)));
+    if (!c.step) HIPCHK(h, hipMalloc(&c.step, sizeof(long long)));
+    HIPCHK(h, hipMemcpyAsync(c.f, h->buf[h->cur], h->buf_bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (h->nparts) HIPCHK(h, hipMemcpyAsync(c.p, h->dparts, sizeof(PartDev) * h->nparts, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(c.step, h->dstep, sizeof(long long), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    c.steps = h->steps;
+    c.cur = h->cur;
+    c.nparts = h->nparts;
+    return LBM_OK;
+}
+
+extern "C" int lbm_checkpoint_restore(lbm_handle* h, int32_t slot) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (slot < 0 || slot >= 8) FAIL(h, LBM_EINVAL, "slot must be in 0..7");
+    Checkpoint& c = h->ck[slot];
+    if (!c.f || c.nparts != h->nparts || !h->finalized) FAIL(h, LBM_ESTATE, "slot %d holds no compatible checkpoint", slot);
+    HIPCHK(h, hipMemcpyAsync(h->buf[c.cur], c.f, h->buf_bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (h->nparts) HIPCHK(h, hipMemcpyAsync(h->dparts, c.p, sizeof(PartDev) * h->nparts, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->dstep, c.step, sizeof(long long), hipMemcpyDeviceToDevice, h->stream));
+    int fl[4] = {0, INT_MAX, 0, 0};
+    HIPCHK(h, hipMemcpyAsync(h->dflags, fl, sizeof(fl), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->cur = c.cur;
+    h->steps = c.steps;
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
+    if (!h || !t) FAIL(h, LBM_EINVAL, "NULL argument");
+    if (t->tile_w != 64 && t->tile_w != 128 && t->tile_w != 256) FAIL(h, LBM_EINVAL, "tile_w must be 64, 128 or 256");
+    if (t->rows_per_thread != 1 && t->rows_per_thread != 2 && t->rows_per_thread != 4)
+        FAIL(h, LBM_EINVAL, "rows_per_thread must be 1, 2 or 4");
+    if (t->persistent_wgs < 0) FAIL(h, LBM_EINVAL, "persistent_wgs must be >= 0");
+    if (t->use_graph != 0 && t->use_graph != 1) FAIL(h, LBM_EINVAL, "use_graph must be 0 or 1");
+    if (t->xcd_remap != 0 && t->xcd_remap != 1) FAIL(h, LBM_EINVAL, "xcd_remap must be 0 or 1");
+    const bool tiles = t->tile_w != h->tune.tile_w || t->rows_per_thread != h->tune.rows_per_thread;
+    h->tune = *t;
+    if (tiles) h->tiles_dirty = true;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t) {
+    if (!h || !t) return LBM_EINVAL;
+    *t = h->tune;
+    return LBM_OK;
+}
+
+extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
+    if (!h || !out_us || reps < 1) FAIL(h, LBM_EINVAL, "bad argument");
+    int r;
+    if ((r = finalize(h)) != LBM_OK) return r;
+    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    const int par0 = h->cur;
+    for (int k = 0; k < 3; ++k) {
+        HIPCHK(h, hipEventRecord(e0, h->stream));
+        for (int i = 0; i < reps; ++i) {
+            StepArgs a = make_args(h, h->cur, par0);
+            if (k == 0) HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+            if (k == 1) {
+                HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+                h->cur = 1 - h->cur;
+            }
+            if (k == 2) HIPCHK(h, launch_traction(h->store, a, h->stream));
+        }
+        HIPCHK(h, hipEventRecord(e1, h->stream));
+        HIPCHK(h, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+        out_us[k] = (k == 2 && h->nparts == 0) ? 0.0 : 1e3 * ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->steps += reps;  // every phase advanced its part of the state reps times
+    return check_flags(h);
+}
+
+extern "C" int64_t lbm_steps_done(const lbm_handle* h) { return h ? h->steps : -1; }
+
+extern "C" const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+extern "C" int lbm_destroy(lbm_handle* h) {
+    if (!h) return LBM_OK;
+    drop_graphs(h);
+    void* ptrs[] = {h->ws_alloc, h->dchan, h->dtiles, h->dparts, h->dxi, h->dnrm, h->dds, h->dpatch,
+                    h->dcontrib, h->dmscr, h->dflags, h->dtflag, h->dstep, h->drec};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& c : h->ck) {
+        if (c.f) (void)hipFree(c.f);
+        if (c.p) (void)hipFree(c.p);
+        if (c.step) (void)hipFree(c.step);
+    }
+    delete h;
+    return LBM_OK;
+}

@@ -1,0 +1,96 @@
+// Internal structures shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmk {
+
+constexpr int kMaxCellsDefault = 8192;   // force-patch cells of one particle (raised from
+                                         // the device's LDS size at init)
+constexpr int kChunk = 32;               // markers per spreading chunk (one u32 mask)
+constexpr int kRecSlots = 1024;          // trajectory ring-buffer depth (steps)
+constexpr int kMaxNeighbours = 8;        // short candidate lists of force patches
+constexpr int kRound = 64;               // markers per round of the particle kernels
+constexpr int kIbmThreads = 9 * kRound;  // one thread per (marker, stencil node)
+
+// One channel: lattice geometry, walls and physical constants.  Read by the
+// kernels through scalar loads (one channel per tile / particle).
+struct ChanDev {
+    int nx, ny, pitch, bcx, bcy;
+    int p_begin, p_end;      // particle index range of this channel
+    int kernel, spread_unit;
+    int pad0;
+    long long off;           // element offset of the channel in a buffer
+    long long plane;         // ny * pitch: elements per population plane
+    double tau, nu;
+    double uw[4][2];
+    double g[2];             // uniform body force on the fluid
+    double grav[2];          // gravity on the particles
+    double rw, alpha, dn;
+    // FP32 copies for the reduced-precision lattice pass
+    float f_omega, f_pref;
+    float f_g[2];
+    float f_uw[4][2];
+    float sc[3], isc[3];     // F16S scales (rest, axis, diagonal) and inverses
+    int tile0, tiles_x;      // first tile of the channel, tiles per tile row
+};
+
+struct TileDev {
+    int chan, x0, y0, pad;
+};
+
+// Rigid particle state (FP64) plus its force patch.
+struct PartDev {
+    double X[2], Xm[2], th, thm;
+    double V[2], Vm[2], Om, Omm;
+    double acc[2], alp;      // accelerations of the previous step
+    double F[2], M;          // force and moment of the last step
+    double m, I, ratio;
+    int chan, mbeg, nm, patch_cap;
+    int bx0, by0, bw, bh;    // patch box in unwrapped lattice coordinates
+    long long patch_off;     // first cell of the patch in the patch pool
+};
+
+struct StepArgs {
+    const void* fin;         // post-collision populations of step n-1
+    void* fout;              // post-collision populations of step n
+    const ChanDev* chan;
+    int nchan;
+    const TileDev* tiles;
+    int ntiles;
+    PartDev* parts;
+    int nparts;
+    int persistent;          // lattice pass: 0 = one WG per tile
+    int xcd_remap;           // lattice pass: contiguous tile blocks per XCD
+    const double2* xi;       // marker pool (body frame)
+    const double2* nrm;
+    const double* ds;
+    double2* patch;          // force patches
+    double2* contrib;        // [markers][9] spread contributions
+    double* mscr;            // [markers][4] traction scratch
+    int* flags;              // [0] unstable, [1] first bad step, [2] capacity
+    long long* dstep;        // steps started so far
+    double* rec;             // [kRecSlots][nparts][10]
+    int max_cells;           // LDS mask capacity of the spreading kernel
+    int* tflag;              // [2][ntiles] tiles touched by a force patch
+    int parity;              // which half of tflag this step sets / reads
+    int tile_w, tile_h;      // tile extent in nodes
+};
+
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
+
+// Launchers (lbm_kernels.hip).
+hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx, int ny,
+                       hipStream_t s);
+hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s);
+hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hipStream_t s);
+hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s);
+hipError_t launch_fields(int store, const StepArgs& a, int chan, int nx, int ny, double* f_out,
+                         double* rho, double* ux, double* uy, hipStream_t s);
+hipError_t launch_set_pop(int store, const StepArgs& a, int chan, int nx, int ny,
+                          const double* f_in, hipStream_t s);
+size_t ibm_lds_bytes(int max_cells);
+size_t ibm_static_lds_bytes();
+
+}  // namespace lbmk

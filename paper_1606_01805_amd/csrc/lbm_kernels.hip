@@ -1,0 +1,1147 @@
+// gfx950 kernels of the coupled LBM / MLS-IBM time step.
+//
+// Per step, in stream order:
+//   ibm_force  one workgroup per particle: marker kinematics, MLS shape
+//              functions at the markers (Sec. 1.2, Eqs. (8)-(10)), velocity
+//              interpolation from the pulled populations, Lagrangian force
+//              (Eq. (11)) and an atomic-free, deterministic spreading of
+//              c_l phi F_l into a per-particle force patch (Eq. (12)).
+//   lattice    one workgroup per tile (or a persistent grid striding over the
+//              tile table of all channels): pull streaming, Zou-He walls,
+//              moments, forced BGK collision (Eqs. (2)-(7)), SoA store.
+//   traction   one workgroup per particle: probe MLS, surface stress, force
+//              and moment (Eqs. (13), (14)), BDF2 (Eqs. (15), (16)), record.
+//
+// Populations are SoA: [channel block][9][ny][pitch], x fastest.  The buffer
+// read by a step holds the post-collision populations of the previous step;
+// pulling f_i(x) = f^c_i(x - e_i) gives the streamed populations on the fly.
+//
+// The FP64 form evaluates every expression in the order of the plain
+// reference formulation (compiled without FMA contraction), so that for the
+// same inputs its lattice arithmetic is the same IEEE operation sequence.
+// The FP32 and FP16S forms keep the deviation d_i = f_i - w_i and compute in
+// FP32.  The immersed-boundary and rigid-body stages are FP64 in every form.
+#include <hip/hip_fp16.h>
+
+#include "lbm_internal.h"
+
+namespace lbmk {
+
+// D2Q9 velocities in the order of Eq. (3) and their weights.
+__device__ __forceinline__ constexpr int ex(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr int ey(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr double wd(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+__device__ __forceinline__ constexpr float wf(int i) {
+    return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+}
+__device__ __forceinline__ constexpr int wclass(int i) { return i == 0 ? 0 : (i < 5 ? 1 : 2); }
+
+template <int ST> struct Sto;
+template <> struct Sto<ST_F64> { using T = double; };
+template <> struct Sto<ST_F32> { using T = float; };
+template <> struct Sto<ST_F16S> { using T = __half; };
+
+__device__ __forceinline__ long long pidx(const ChanDev& c, int i, int y, int x) {
+    return c.off + (long long)i * c.plane + (long long)y * c.pitch + x;
+}
+
+// Source node of population i for a pull at (x, y); false when it lies beyond
+// a wall (the population is then reconstructed by the wall condition).
+__device__ __forceinline__ bool pull_src(const ChanDev& c, int i, int x, int y, int& xs, int& ys) {
+    xs = x - ex(i);
+    ys = y - ey(i);
+    bool ok = true;
+    if (c.bcx == 0) {
+        xs = xs < 0 ? xs + c.nx : (xs >= c.nx ? xs - c.nx : xs);
+    } else if (xs < 0 || xs >= c.nx) {
+        ok = false;
+    }
+    if (c.bcy == 0) {
+        ys = ys < 0 ? ys + c.ny : (ys >= c.ny ? ys - c.ny : ys);
+    } else if (ys < 0 || ys >= c.ny) {
+        ok = false;
+    }
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 form: populations f_i, expressions in reference order.
+// ---------------------------------------------------------------------------
+// Zou-He known-velocity wall (Sec. 1.1): mass and normal momentum fix rho,
+// bounce-back of the non-equilibrium normal population, tangential momentum
+// for the two diagonals; target momentum m = rho u_w - g/2.
+__device__ __forceinline__ void zouhe_f64(int side, double f[9], double uwx, double uwy,
+                                          double gx, double gy) {
+    double rho, mx, my;
+    if (side == 2) {
+        rho = (f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]) - 0.5 * gy) / (1.0 - uwy);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[2] = f[4] + 2.0 * my / 3.0;
+        f[5] = f[7] - 0.5 * (f[1] - f[3]) + 0.5 * mx + my / 6.0;
+        f[6] = f[8] + 0.5 * (f[1] - f[3]) - 0.5 * mx + my / 6.0;
+    } else if (side == 3) {
+        rho = (f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]) + 0.5 * gy) / (1.0 + uwy);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[4] = f[2] - 2.0 * my / 3.0;
+        f[7] = f[5] + 0.5 * (f[1] - f[3]) - 0.5 * mx - my / 6.0;
+        f[8] = f[6] - 0.5 * (f[1] - f[3]) + 0.5 * mx - my / 6.0;
+    } else if (side == 0) {
+        rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7]) - 0.5 * gx) / (1.0 - uwx);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[1] = f[3] + 2.0 * mx / 3.0;
+        f[5] = f[7] - 0.5 * (f[2] - f[4]) + mx / 6.0 + 0.5 * my;
+        f[8] = f[6] + 0.5 * (f[2] - f[4]) + mx / 6.0 - 0.5 * my;
+    } else {
+        rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8]) + 0.5 * gx) / (1.0 + uwx);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[3] = f[1] - 2.0 * mx / 3.0;
+        f[7] = f[5] + 0.5 * (f[2] - f[4]) - mx / 6.0 - 0.5 * my;
+        f[6] = f[8] - 0.5 * (f[2] - f[4]) - mx / 6.0 + 0.5 * my;
+    }
+}
+
+__device__ __forceinline__ void walls_f64(const ChanDev& c, int x, int y, double f[9]) {
+    if (c.bcy == 1) {
+        if (y == 0) zouhe_f64(2, f, c.uw[2][0], c.uw[2][1], c.g[0], c.g[1]);
+        else if (y == c.ny - 1) zouhe_f64(3, f, c.uw[3][0], c.uw[3][1], c.g[0], c.g[1]);
+    }
+    if (c.bcx == 1) {
+        if (x == 0) zouhe_f64(0, f, c.uw[0][0], c.uw[0][1], c.g[0], c.g[1]);
+        else if (x == c.nx - 1) zouhe_f64(1, f, c.uw[1][0], c.uw[1][1], c.g[0], c.g[1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduced forms: deviations d_i = f_i - w_i in FP32.
+// ---------------------------------------------------------------------------
+template <int ST>
+__device__ __forceinline__ float load_dev(const typename Sto<ST>::T* p, long long k, int i,
+                                          const ChanDev& c) {
+    if constexpr (ST == ST_F32) {
+        return p[k];
+    } else {
+        return __half2float(p[k]) * c.isc[wclass(i)];
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void store_dev(typename Sto<ST>::T* p, long long k, int i, float d,
+                                          const ChanDev& c) {
+    if constexpr (ST == ST_F32) {
+        p[k] = d;
+    } else {
+        p[k] = __float2half_rn(d * c.sc[wclass(i)]);
+    }
+}
+
+// The Zou-He closure of zouhe_f64 written for deviations: the weights of the
+// known populations entering rho sum to 1, and w_i cancels in every
+// difference.
+__device__ __forceinline__ void zouhe_dev(int side, float d[9], float uwx, float uwy, float gx,
+                                          float gy) {
+    float drho, rho, mx, my;
+    if (side == 2) {
+        float s = d[0] + d[1] + d[3] + 2.0f * (d[4] + d[7] + d[8]);
+        drho = (s - 0.5f * gy + uwy) / (1.0f - uwy);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[2] = d[4] + (2.0f / 3.0f) * my;
+        d[5] = d[7] - 0.5f * (d[1] - d[3]) + 0.5f * mx + my * (1.0f / 6.0f);
+        d[6] = d[8] + 0.5f * (d[1] - d[3]) - 0.5f * mx + my * (1.0f / 6.0f);
+    } else if (side == 3) {
+        float s = d[0] + d[1] + d[3] + 2.0f * (d[2] + d[5] + d[6]);
+        drho = (s + 0.5f * gy - uwy) / (1.0f + uwy);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[4] = d[2] - (2.0f / 3.0f) * my;
+        d[7] = d[5] + 0.5f * (d[1] - d[3]) - 0.5f * mx - my * (1.0f / 6.0f);
+        d[8] = d[6] - 0.5f * (d[1] - d[3]) + 0.5f * mx - my * (1.0f / 6.0f);
+    } else if (side == 0) {
+        float s = d[0] + d[2] + d[4] + 2.0f * (d[3] + d[6] + d[7]);
+        drho = (s - 0.5f * gx + uwx) / (1.0f - uwx);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[1] = d[3] + (2.0f / 3.0f) * mx;
+        d[5] = d[7] - 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) + 0.5f * my;
+        d[8] = d[6] + 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) - 0.5f * my;
+    } else {
+        float s = d[0] + d[2] + d[4] + 2.0f * (d[1] + d[5] + d[8]);
+        drho = (s + 0.5f * gx - uwx) / (1.0f + uwx);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[3] = d[1] - (2.0f / 3.0f) * mx;
+        d[7] = d[5] + 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) - 0.5f * my;
+        d[6] = d[8] - 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) + 0.5f * my;
+    }
+}
+
+__device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float d[9]) {
+    if (c.bcy == 1) {
+        if (y == 0) zouhe_dev(2, d, c.f_uw[2][0], c.f_uw[2][1], c.f_g[0], c.f_g[1]);
+        else if (y == c.ny - 1) zouhe_dev(3, d, c.f_uw[3][0], c.f_uw[3][1], c.f_g[0], c.f_g[1]);
+    }
+    if (c.bcx == 1) {
+        if (x == 0) zouhe_dev(0, d, c.f_uw[0][0], c.f_uw[0][1], c.f_g[0], c.f_g[1]);
+        else if (x == c.nx - 1) zouhe_dev(1, d, c.f_uw[1][0], c.f_uw[1][1], c.f_g[0], c.f_g[1]);
+    }
+}
+
+// Streamed populations f^n at one node, as FP64 f_i (all forms).
+template <int ST>
+__device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c, int x, int y,
+                                              double f[9]) {
+    if constexpr (ST == ST_F64) {
+        const double* p = (const double*)fin;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int xs, ys;
+            f[i] = pull_src(c, i, x, y, xs, ys) ? p[pidx(c, i, ys, xs)] : 0.0;
+        }
+        walls_f64(c, x, y, f);
+    } else {
+        using T = typename Sto<ST>::T;
+        const T* p = (const T*)fin;
+        float d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int xs, ys;
+            d[i] = pull_src(c, i, x, y, xs, ys) ? load_dev<ST>(p, pidx(c, i, ys, xs), i, c) : 0.0f;
+        }
+        walls_dev(c, x, y, d);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = wd(i) + (double)d[i];
+    }
+}
+
+// Moments of Eqs. (6), (7) before the IB force is known: rho and
+// j* = sum f e + g/2, summed over i in ascending order.
+__device__ __forceinline__ void moments_f64(const double f[9], const ChanDev& c, double& rho,
+                                            double& jx, double& jy) {
+    rho = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rho += f[i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) jx += f[i] * (double)ex(i);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) jy += f[i] * (double)ey(i);
+    jx += 0.5 * c.g[0];
+    jy += 0.5 * c.g[1];
+}
+
+// Force patches of a channel's particles covering node (x, y), summed in
+// ascending particle order.  Boxes hold wrapped origins on periodic axes.
+__device__ __forceinline__ void patch_force(const StepArgs& a, const ChanDev& c, int x, int y,
+                                            double& fx, double& fy) {
+    fx = 0.0;
+    fy = 0.0;
+    for (int q = c.p_begin; q < c.p_end; ++q) {
+        const PartDev& P = a.parts[q];
+        int dx = x - P.bx0, dy = y - P.by0;
+        if (c.bcx == 0 && dx < 0) dx += c.nx;
+        if (c.bcy == 0 && dy < 0) dy += c.ny;
+        if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
+            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            fx += v.x;
+            fy += v.y;
+        }
+    }
+}
+
+// The same sum over a short list of candidate particles (ascending).
+__device__ __forceinline__ void patch_force_list(const StepArgs& a, const ChanDev& c,
+                                                 const int* list, int n, int x, int y,
+                                                 double& fx, double& fy) {
+    fx = 0.0;
+    fy = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const PartDev& P = a.parts[list[j]];
+        int dx = x - P.bx0, dy = y - P.by0;
+        if (c.bcx == 0 && dx < 0) dx += c.nx;
+        if (c.bcy == 0 && dy < 0) dy += c.ny;
+        if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
+            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            fx += v.x;
+            fy += v.y;
+        }
+    }
+}
+
+// Do the boxes [x0, x0 + w) x [y0, y0 + h) and [u0, u0 + p) x [v0, v0 + q)
+// intersect?  Origins may be unwrapped; periodic axes compare modulo n.
+__device__ __forceinline__ bool span_overlap(int x0, int w, int u0, int p, int n, bool per) {
+    if (!per) return x0 < u0 + p && u0 < x0 + w;
+    if (w >= n || p >= n) return true;
+    int d1 = (u0 - x0) % n, d2 = (x0 - u0) % n;
+    if (d1 < 0) d1 += n;
+    if (d2 < 0) d2 += n;
+    return d1 < w || d2 < p;
+}
+
+__device__ __forceinline__ bool boxes_overlap(const ChanDev& c, int x0, int y0, int w, int h,
+                                              int u0, int v0, int p, int q) {
+    return span_overlap(x0, w, u0, p, c.nx, c.bcx == 0) && span_overlap(y0, h, v0, q, c.ny, c.bcy == 0);
+}
+
+// ---------------------------------------------------------------------------
+// MLS transfer operator (Sec. 1.2, Eqs. (8)-(10)) at one point, FP64.
+// 3x3 nodes around the nearest node (round half up); shifted linear basis
+// (1, x_k - x, y_k - y); nodes beyond a wall-bounded edge are dropped; the 3x3
+// moment matrix is inverted through its adjugate.  Outputs the anchor, the
+// validity mask and the value / x-derivative / y-derivative weights.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double kernel_weight(int kind, double r, double alpha) {
+    if (r > 1.0) return 0.0;
+    if (kind == 0) {
+        double q = r / alpha;
+        return exp(-(q * q));
+    } else if (kind == 1) {
+        return 2.0 / 3.0 - 4.0 * r * r + 4.0 * r * r * r;
+    } else if (kind == 2) {
+        return 1.0 - 6.0 * r * r + 8.0 * r * r * r - 3.0 * r * r * r * r;
+    }
+    return 0.25 * (1.0 + cos(3.14159265358979323846 / 2.0 * r));
+}
+
+__device__ __forceinline__ int wrapc(int v, int n, int periodic) {
+    if (!periodic) return v;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: immersed-boundary force and spreading (one workgroup / particle).
+//
+// Markers are processed in rounds of 64 by 576 threads, one per (marker,
+// stencil node) pair: each pair thread evaluates one MLS weight and pulls the
+// moments of one stencil node; the k = 0 thread of each marker then assembles
+// the 3x3 moment matrix and interpolant in ascending node order, exactly as
+// the reference formulation does, and leaves the marker's contributions
+// c_l phi_k F_l in LDS for the spreading of the same round.
+// ---------------------------------------------------------------------------
+struct Marker {
+    double rx, ry, xl, yl;
+    int i0, j0;
+};
+
+__device__ __forceinline__ Marker marker_at(const StepArgs& a, int idx, double X0, double X1,
+                                            double cs, double sn) {
+    Marker m;
+    const double2 x = a.xi[idx];
+    m.rx = cs * x.x - sn * x.y;
+    m.ry = sn * x.x + cs * x.y;
+    m.xl = X0 + m.rx;
+    m.yl = X1 + m.ry;
+    m.i0 = (int)floor(m.xl + 0.5);
+    m.j0 = (int)floor(m.yl + 0.5);
+    return m;
+}
+
+// Stencil node k of the 3x3 support around anchor (i0, j0): distance
+// components d = x_k - x, wrapped node, validity (beyond a wall-bounded edge
+// the node is dropped).
+__device__ __forceinline__ bool stencil_node(const ChanDev& c, int i0, int j0, int k, double x,
+                                             double y, double& dx, double& dy, int& ni, int& nj) {
+    const int ii = i0 + k % 3 - 1, jj = j0 + k / 3 - 1;
+    dx = (double)ii - x;
+    dy = (double)jj - y;
+    ni = wrapc(ii, c.nx, c.bcx == 0);
+    nj = wrapc(jj, c.ny, c.bcy == 0);
+    return (c.bcx == 0 || (ii >= 0 && ii < c.nx)) && (c.bcy == 0 || (jj >= 0 && jj < c.ny));
+}
+
+__device__ __forceinline__ bool node_valid(const ChanDev& c, int ii, int jj) {
+    return (c.bcx == 0 || (ii >= 0 && ii < c.nx)) && (c.bcy == 0 || (jj >= 0 && jj < c.ny));
+}
+
+__device__ __forceinline__ double stencil_weight(const ChanDev& c, double dx, double dy) {
+    const double r = sqrt(dx * dx + dy * dy) / c.rw;
+    return kernel_weight(c.kernel, r, c.alpha);
+}
+
+// Inverse (through the adjugate) of the moment matrix of Eq. (9), accumulated
+// over the valid nodes in ascending k from the weights in w[0..8].
+struct MlsInv {
+    double i00, i01, i02, i11, i12, i22;
+};
+
+__device__ __forceinline__ MlsInv mls_inverse(const ChanDev& c, const double* w, int i0, int j0,
+                                              double x, double y, bool all) {
+    double A00 = 0.0, A01 = 0.0, A02 = 0.0, A11 = 0.0, A12 = 0.0, A22 = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
+        if (!node_valid(c, ii, jj)) continue;
+        const double dx = (double)ii - x, dy = (double)jj - y, wk = w[q];
+        A00 += wk;
+        A01 += wk * dx;
+        A02 += wk * dy;
+        A11 += wk * dx * dx;
+        A12 += wk * dx * dy;
+        A22 += wk * dy * dy;
+    }
+    const double c00 = A11 * A22 - A12 * A12;
+    const double c01 = A02 * A12 - A01 * A22;
+    const double c02 = A01 * A12 - A02 * A11;
+    const double det = A00 * c00 + A01 * c01 + A02 * c02;
+    MlsInv r;
+    r.i00 = c00 / det;
+    r.i01 = c01 / det;
+    r.i02 = c02 / det;
+    r.i11 = r.i12 = r.i22 = 0.0;
+    if (all) {
+        const double c11 = A00 * A22 - A02 * A02;
+        const double c12 = A01 * A02 - A00 * A12;
+        const double c22 = A00 * A11 - A01 * A01;
+        r.i11 = c11 / det;
+        r.i12 = c12 / det;
+        r.i22 = c22 / det;
+    }
+    return r;
+}
+
+// Mark the lattice tiles that a patch box [x0, x0 + w) x [y0, y0 + h)
+// (unwrapped coordinates) overlaps, so the lattice pass looks up particle
+// forces only there.  Periodic ranges split into at most two pieces.
+__device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, int x0, int y0,
+                                           int w, int h, int tid, int nthr) {
+    int xr[2][2], yr[2][2], nxr = 0, nyr = 0;
+    auto split = [](int lo, int len, int n, bool per, int r[2][2]) {
+        int cnt = 0;
+        if (per) {
+            int s0 = wrapc(lo, n, 1);
+            int e0 = s0 + len - 1;
+            if (e0 < n) {
+                r[0][0] = s0; r[0][1] = e0; cnt = 1;
+            } else {
+                r[0][0] = s0; r[0][1] = n - 1; r[1][0] = 0; r[1][1] = e0 - n; cnt = 2;
+            }
+        } else {
+            int s0 = max(lo, 0), e0 = min(lo + len - 1, n - 1);
+            if (s0 <= e0) { r[0][0] = s0; r[0][1] = e0; cnt = 1; }
+        }
+        return cnt;
+    };
+    nxr = split(x0, w, c.nx, c.bcx == 0, xr);
+    nyr = split(y0, h, c.ny, c.bcy == 0, yr);
+    int* fl = a.tflag + (long long)a.parity * a.ntiles;
+    for (int p = 0; p < nxr; ++p)
+        for (int q = 0; q < nyr; ++q) {
+            const int tx0 = xr[p][0] / a.tile_w, tx1 = xr[p][1] / a.tile_w;
+            const int ty0 = yr[q][0] / a.tile_h, ty1 = yr[q][1] / a.tile_h;
+            const int ntx = tx1 - tx0 + 1, cnt = ntx * (ty1 - ty0 + 1);
+            for (int t = tid; t < cnt; t += nthr)
+                atomicOr(&fl[c.tile0 + (ty0 + t / ntx) * c.tiles_x + tx0 + t % ntx], 1);
+        }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
+    extern __shared__ unsigned long long smask[];  // [max_cells] markers anchored per cell
+    __shared__ double s_w[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
+    __shared__ double2 s_con[kIbmThreads];         // c_l phi_k F_l of the round
+    __shared__ int2 s_anc[kRound];
+    __shared__ int box[4];  // min i0, min j0, max i0, max j0
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
+    if ((int)blockIdx.x >= a.nparts) return;
+    PartDev* P = a.parts + blockIdx.x;
+    const ChanDev& c = a.chan[P->chan];
+    const int nm = P->nm, mb = P->mbeg;
+    const double X0 = P->X[0], X1 = P->X[1], th = P->th;
+    const double V0 = P->V[0], V1 = P->V[1], Om = P->Om;
+    // A particle whose state is no longer finite, or far outside any
+    // lattice, is flagged and skipped: its stencil anchors would be
+    // meaningless and must never index memory.
+    const double lim = 1e8;
+    if (!(fabs(X0) < lim) || !(fabs(X1) < lim) || !(fabs(th) < lim)) {
+        if (tid == 0) {
+            P->bw = 0;
+            P->bh = 0;
+            a.flags[0] = 1;
+            atomicMin(&a.flags[1], (int)(*a.dstep - 1));
+        }
+        return;
+    }
+    const double cs = cos(th), sn = sin(th);
+    if (tid == 0) {
+        box[0] = box[1] = 0x7fffffff;
+        box[2] = box[3] = -0x7fffffff;
+    }
+    __syncthreads();
+
+    // Bounding box of the marker anchors: the force patch.  Reduced within
+    // each wave first, then one LDS atomic per wave and bound.
+    {
+        int mn0 = 0x7fffffff, mn1 = 0x7fffffff, mx0 = -0x7fffffff, mx1 = -0x7fffffff;
+        for (int l = tid; l < nm; l += blockDim.x) {
+            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+            mn0 = min(mn0, m.i0);
+            mn1 = min(mn1, m.j0);
+            mx0 = max(mx0, m.i0);
+            mx1 = max(mx1, m.j0);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            mn0 = min(mn0, __shfl_xor(mn0, o));
+            mn1 = min(mn1, __shfl_xor(mn1, o));
+            mx0 = max(mx0, __shfl_xor(mx0, o));
+            mx1 = max(mx1, __shfl_xor(mx1, o));
+        }
+        if ((tid & 63) == 0 && tid < nm) {
+            atomicMin(&box[0], mn0);
+            atomicMin(&box[1], mn1);
+            atomicMax(&box[2], mx0);
+            atomicMax(&box[3], mx1);
+        }
+    }
+    __syncthreads();
+    const int bx0u = box[0] - 1, by0u = box[1] - 1;
+    const long long bwl = (long long)box[2] - box[0] + 3, bhl = (long long)box[3] - box[1] + 3;
+    if (bwl > c.nx || bhl > c.ny || bwl * bhl > P->patch_cap || bwl * bhl > a.max_cells) {
+        if (tid == 0) {
+            atomicOr(&a.flags[2], 1);
+            P->bw = 0;
+            P->bh = 0;
+        }
+        return;
+    }
+    const int bw = (int)bwl, bh = (int)bhl;
+    const int ncell = bw * bh;
+    double2* patch = a.patch + P->patch_off;
+    for (int k = tid; k < ncell; k += blockDim.x) {
+        patch[k] = make_double2(0.0, 0.0);
+        smask[k] = 0ull;
+    }
+    mark_tiles(a, c, bx0u, by0u, bw, bh, tid, blockDim.x);
+    if (tid == 0) {
+        P->bx0 = wrapc(bx0u, c.nx, c.bcx == 0);
+        P->by0 = wrapc(by0u, c.ny, c.bcy == 0);
+        P->bw = bw;
+        P->bh = bh;
+    }
+    __syncthreads();
+
+    const int lo = tid / 9, k = tid % 9;
+    for (int r0 = 0; r0 < nm; r0 += kRound) {
+        const int l = r0 + lo;
+        const bool act = l < nm;
+        // (1) one weight and the force-free velocity u* = j*/rho of one node
+        if (act) {
+            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+            double dx, dy;
+            int ni, nj;
+            double w = 0.0, ux = 0.0, uy = 0.0;
+            if (stencil_node(c, m.i0, m.j0, k, m.xl, m.yl, dx, dy, ni, nj)) {
+                w = stencil_weight(c, dx, dy);
+                double f[9], rho, jx, jy;
+                pull_node_f64<ST>(a.fin, c, ni, nj, f);
+                moments_f64(f, c, rho, jx, jy);
+                ux = jx / rho;
+                uy = jy / rho;
+            }
+            s_w[tid] = w;
+            s_ux[tid] = ux;
+            s_uy[tid] = uy;
+            if (k == 0) s_anc[lo] = make_int2(m.i0, m.j0);
+        }
+        __syncthreads();
+        // (2) per marker, all in the first wave (thread lm leads marker
+        // r0 + lm): phi, U = sum phi u* (k ascending), F = U_b - U (dt = 1),
+        // contributions; its bit in the mask of its anchor cell
+        if (tid < kRound && r0 + tid < nm) {
+            const int lm = tid, l = r0 + lm;
+            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+            const int lo = lm;
+            const double* w = s_w + lo * 9;
+            const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, false);
+            double Ux = 0.0, Uy = 0.0;
+            for (int q = 0; q < 9; ++q) {
+                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
+                if (!node_valid(c, ii, jj)) continue;
+                const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
+                const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
+                Ux += phi * s_ux[lo * 9 + q];
+                Uy += phi * s_uy[lo * 9 + q];
+            }
+            const double ubx = V0 - Om * m.ry;
+            const double uby = V1 + Om * m.rx;
+            const double Fx = ubx - Ux, Fy = uby - Uy;
+            const double cl = c.spread_unit ? 1.0 : a.ds[mb + l];
+            for (int q = 0; q < 9; ++q) {
+                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
+                double2 v = make_double2(0.0, 0.0);
+                if (node_valid(c, ii, jj)) {
+                    const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
+                    const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
+                    v = make_double2(cl * phi * Fx, cl * phi * Fy);
+                }
+                s_con[lo * 9 + q] = v;
+            }
+            atomicOr(&smask[(m.j0 - by0u) * bw + (m.i0 - bx0u)], 1ull << lo);
+        }
+        __syncthreads();
+        // (3) spreading f_lb(x_k) = sum_l c_l phi^l_k F_l: the lowest marker
+        // of the round covering a node owns it and adds the round's terms in
+        // ascending marker order onto the sums of the earlier rounds, so each
+        // node receives its terms in ascending marker order, with no float
+        // atomics.
+        if (act) {
+            const int2 an = s_anc[lo];
+            const int ni = an.x + k % 3 - 1, nj = an.y + k / 3 - 1;
+            if (node_valid(c, ni, nj)) {
+                unsigned long long msk = 0ull;
+                for (int db = -1; db <= 1; ++db) {
+                    const int cy = nj + db - by0u;
+                    if (cy < 0 || cy >= bh) continue;
+                    for (int da = -1; da <= 1; ++da) {
+                        const int cx = ni + da - bx0u;
+                        if (cx < 0 || cx >= bw) continue;
+                        msk |= smask[cy * bw + cx];
+                    }
+                }
+                if (!(msk & ((1ull << lo) - 1ull))) {
+                    const int cell = (nj - by0u) * bw + (ni - bx0u);
+                    double2 acc = r0 == 0 ? make_double2(0.0, 0.0) : patch[cell];
+                    while (msk) {
+                        const int b = __ffsll((long long)msk) - 1;
+                        msk &= msk - 1ull;
+                        const int2 a2 = s_anc[b];
+                        const int k2 = 3 * (nj - a2.y + 1) + (ni - a2.x + 1);
+                        const double2 v = s_con[b * 9 + k2];
+                        acc.x += v.x;
+                        acc.y += v.y;
+                    }
+                    patch[cell] = acc;
+                }
+            }
+        }
+        __syncthreads();
+        if (act && k == 0) smask[(s_anc[lo].y - by0u) * bw + (s_anc[lo].x - bx0u)] = 0ull;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: the lattice pass.
+// ---------------------------------------------------------------------------
+// FP64 form, reference expression order.
+__device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c, int x,
+                                                  int y, const int* list, int nlist) {
+    const double* fin = (const double*)a.fin;
+    double* fout = (double*)a.fout;
+    double f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int xs, ys;
+        f[i] = pull_src(c, i, x, y, xs, ys) ? fin[pidx(c, i, ys, xs)] : 0.0;
+    }
+    walls_f64(c, x, y, f);
+    double rho, jx, jy;
+    moments_f64(f, c, rho, jx, jy);
+    double flbx = 0.0, flby = 0.0;
+    if (nlist > kMaxNeighbours) patch_force(a, c, x, y, flbx, flby);
+    else if (nlist > 0) patch_force_list(a, c, list, nlist, x, y, flbx, flby);
+    const double gx = c.g[0], gy = c.g[1];
+    const double ux = (jx + 0.5 * flbx) / rho;
+    const double uy = (jy + 0.5 * flby) / rho;
+    const double Gx = gx + flbx;
+    const double Gy = gy + flby;
+    const double usq = ux * ux + uy * uy;
+    const double tau = c.tau;
+    const double pref = 1.0 - 1.0 / (2.0 * tau);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double exi = (double)ex(i), eyi = (double)ey(i);
+        const double eu = exi * ux + eyi * uy;
+        const double feq = wd(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        const double Fi = pref * wd(i) * ((3.0 * (exi - ux) + 9.0 * eu * exi) * Gx +
+                                          (3.0 * (eyi - uy) + 9.0 * eu * eyi) * Gy);
+        fout[pidx(c, i, y, x)] = f[i] - (f[i] - feq) / tau + Fi;
+    }
+    if (!(rho > 0.0) || !isfinite(rho)) {
+        a.flags[0] = 1;
+        atomicMin(&a.flags[1], (int)(*a.dstep - 1));
+    }
+}
+
+// Reduced forms: deviations in FP32.
+template <int ST>
+__device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c, int x,
+                                                  int y, const int* list, int nlist) {
+    using T = typename Sto<ST>::T;
+    const T* fin = (const T*)a.fin;
+    T* fout = (T*)a.fout;
+    float d[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int xs, ys;
+        d[i] = pull_src(c, i, x, y, xs, ys) ? load_dev<ST>(fin, pidx(c, i, ys, xs), i, c) : 0.0f;
+    }
+    walls_dev(c, x, y, d);
+    const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    const float rho = 1.0f + drho;
+    float flbx = 0.0f, flby = 0.0f;
+    if (nlist > 0) {
+        double fx, fy;
+        if (nlist > kMaxNeighbours) patch_force(a, c, x, y, fx, fy);
+        else patch_force_list(a, c, list, nlist, x, y, fx, fy);
+        flbx = (float)fx;
+        flby = (float)fy;
+    }
+    const float gx = c.f_g[0], gy = c.f_g[1];
+    const float jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]) + 0.5f * (gx + flbx);
+    const float jy = ((d[2] - d[4]) + (d[5] + d[6])) - (d[7] + d[8]) + 0.5f * (gy + flby);
+    const float irho = 1.0f / rho;
+    const float ux = jx * irho, uy = jy * irho;
+    const float Gx = gx + flbx, Gy = gy + flby;
+    const float usq = ux * ux + uy * uy;
+    const float om = c.f_omega, pref = c.f_pref;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float exi = (float)ex(i), eyi = (float)ey(i);
+        const float eu = exi * ux + eyi * uy;
+        const float deq = wf(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * usq));
+        const float Fi = pref * wf(i) * ((3.0f * (exi - ux) + 9.0f * eu * exi) * Gx +
+                                         (3.0f * (eyi - uy) + 9.0f * eu * eyi) * Gy);
+        store_dev<ST>(fout, pidx(c, i, y, x), i, d[i] + (deq - d[i]) * om + Fi, c);
+    }
+    if (!(rho > 0.0f) || !isfinite(rho)) {
+        a.flags[0] = 1;
+        atomicMin(&a.flags[1], (int)(*a.dstep - 1));
+    }
+}
+
+template <int ST, int TW, int NPT>
+__global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int stride = a.persistent ? (int)gridDim.x : a.ntiles;
+    const int* fl = a.tflag + (long long)a.parity * a.ntiles;
+    int* fl_next = a.tflag + (long long)(1 - a.parity) * a.ntiles;
+    // Workgroups are dispatched round-robin over the 8 XCDs.  With the remap
+    // (one workgroup per tile, grid rounded up to a multiple of 8) XCD x
+    // takes the contiguous tile block [x * per, (x + 1) * per).
+    int t0 = blockIdx.x;
+    if (a.xcd_remap && !a.persistent) {
+        const int per = (int)gridDim.x / 8;
+        t0 = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    }
+    for (int t = t0; t < a.ntiles; t += stride) {
+        const TileDev tl = a.tiles[t];
+        const ChanDev& c = a.chan[tl.chan];
+        const int x = tl.x0 + lx;
+        // force patches touch this tile?  (set by the particle kernel of this
+        // step; the other half is cleared for the next step)  Then list the
+        // channel's particles whose patch boxes overlap the tile.
+        const bool hasf = fl[t] != 0;
+        if (threadIdx.x == 0) fl_next[t] = 0;
+        int nlist = 0;
+        int list[kMaxNeighbours];
+        if (hasf) {
+            for (int q = c.p_begin; q < c.p_end; ++q) {
+                const PartDev& P = a.parts[q];
+                if (P.bw > 0 && boxes_overlap(c, tl.x0, tl.y0, TW, (256 / TW) * NPT, P.bx0, P.by0, P.bw, P.bh)) {
+                    if (nlist < kMaxNeighbours) list[nlist] = q;
+                    ++nlist;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int y = tl.y0 + ly * NPT + r;
+            if (x < c.nx && y < c.ny) {
+                if constexpr (ST == ST_F64) collide_store_f64(a, c, x, y, list, nlist);
+                else collide_store_dev<ST>(a, c, x, y, list, nlist);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 3: surface stress, force, moment and BDF2 (one workgroup / particle).
+// Pair threads (marker, probe-stencil node) evaluate one weight and the
+// corrected fields of one node; the k = 0 thread of each marker builds the
+// probe's MLS value and gradient weights and the marker's traction.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
+    __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
+    __shared__ double s_t[3][1024];
+    __shared__ double sums[3];
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x >= a.nparts) return;
+    PartDev* P = a.parts + blockIdx.x;
+    const ChanDev& c = a.chan[P->chan];
+    const int nm = P->nm, mb = P->mbeg;
+    const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
+    const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
+    const double nu = c.nu, dn = c.dn;
+    const bool skip = P->bw <= 0;  // flagged by the force stage
+    const double cs = skip ? 1.0 : cos(th), sn = skip ? 0.0 : sin(th);
+    const int lo = tid / 9, k = tid % 9;
+    // Particles of the channel whose force patches can reach this particle's
+    // probe stencils (its own box grown by the probe reach), ascending.
+    __shared__ int s_nb[kMaxNeighbours];
+    __shared__ int s_nnb;
+    if (tid == 0) {
+        int n = 0;
+        const int grow = (int)ceil(dn) + 2;
+        for (int q = c.p_begin; q < c.p_end; ++q) {
+            const PartDev& Q = a.parts[q];
+            if (Q.bw <= 0) continue;
+            if (boxes_overlap(c, P->bx0 - grow, P->by0 - grow, P->bw + 2 * grow, P->bh + 2 * grow,
+                              Q.bx0, Q.by0, Q.bw, Q.bh)) {
+                if (n < kMaxNeighbours) s_nb[n] = q;
+                ++n;
+            }
+        }
+        s_nnb = n;
+    }
+    __syncthreads();
+    const int nnb = s_nnb;
+
+    for (int r0 = 0; r0 < (skip ? 0 : nm); r0 += kRound) {
+        const int l = r0 + lo;
+        const bool act = l < nm;
+        if (act) {
+            double rx, ry, nxl, nyl, xp, yp;
+            int i0, j0;
+            const double2 x = a.xi[mb + l], nb = a.nrm[mb + l];
+            rx = cs * x.x - sn * x.y;
+            ry = sn * x.x + cs * x.y;
+            nxl = cs * nb.x - sn * nb.y;
+            nyl = sn * nb.x + cs * nb.y;
+            xp = X0 + rx + dn * nxl;
+            yp = X1 + ry + dn * nyl;
+            i0 = (int)floor(xp + 0.5);
+            j0 = (int)floor(yp + 0.5);
+            (void)ry;
+            double dx, dy;
+            int ni, nj;
+            double w = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
+            if (stencil_node(c, i0, j0, k, xp, yp, dx, dy, ni, nj)) {
+                w = stencil_weight(c, dx, dy);
+                double f[9], jx, jy, fx, fy;
+                pull_node_f64<ST>(a.fin, c, ni, nj, f);
+                moments_f64(f, c, rho, jx, jy);
+                if (nnb <= kMaxNeighbours) patch_force_list(a, c, s_nb, nnb, ni, nj, fx, fy);
+                else patch_force(a, c, ni, nj, fx, fy);
+                ux = (jx + 0.5 * fx) / rho;
+                uy = (jy + 0.5 * fy) / rho;
+            }
+            s_w[tid] = w;
+            s_r[tid] = rho;
+            s_ux[tid] = ux;
+            s_uy[tid] = uy;
+        }
+        __syncthreads();
+        if (tid < kRound && r0 + tid < nm) {
+            // marker r0 + lm, led from the first wave
+            const int lm = tid, l = r0 + lm, lo = lm;
+            const double2 x = a.xi[mb + l], nb = a.nrm[mb + l];
+            const double rx = cs * x.x - sn * x.y;
+            const double ry = sn * x.x + cs * x.y;
+            const double nxl = cs * nb.x - sn * nb.y;
+            const double nyl = sn * nb.x + cs * nb.y;
+            const double xp = X0 + rx + dn * nxl;
+            const double yp = X1 + ry + dn * nyl;
+            const int i0 = (int)floor(xp + 0.5);
+            const int j0 = (int)floor(yp + 0.5);
+            const double* w = s_w + lo * 9;
+            const MlsInv iv = mls_inverse(c, w, i0, j0, xp, yp, true);
+            double rP = 0.0, dudx = 0.0, dudy = 0.0, dvdx = 0.0, dvdy = 0.0;
+            for (int q = 0; q < 9; ++q) {
+                const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
+                if (!node_valid(c, ii, jj)) continue;
+                const double dx = (double)ii - xp, dy = (double)jj - yp;
+                const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
+                const double dpx = w[q] * (iv.i01 + iv.i11 * dx + iv.i12 * dy);
+                const double dpy = w[q] * (iv.i02 + iv.i12 * dx + iv.i22 * dy);
+                const double rq = s_r[lo * 9 + q], uq = s_ux[lo * 9 + q], vq = s_uy[lo * 9 + q];
+                rP += phi * rq;
+                dudx += dpx * uq;
+                dudy += dpy * uq;
+                dvdx += dpx * vq;
+                dvdy += dpy * vq;
+            }
+            const double pP = (rP - 1.0) / 3.0;
+            const double txx = nu * (2.0 * dudx);
+            const double txy = nu * (dudy + dvdx);
+            const double tyy = nu * (2.0 * dvdy);
+            const double alx = acc0 - alp * ry - Om * Om * rx;
+            const double aly = acc1 + alp * rx - Om * Om * ry;
+            const double pl = pP + dn * (alx * nxl + aly * nyl);
+            const double tx = txx * nxl + txy * nyl - pl * nxl;
+            const double ty = txy * nxl + tyy * nyl - pl * nyl;
+            const double S = a.ds[mb + l];
+            s_t[0][l] = tx * S;
+            s_t[1][l] = ty * S;
+            s_t[2][l] = (rx * ty - ry * tx) * S;
+        }
+        __syncthreads();
+    }
+    // Force and moment: sums over the markers in ascending order.
+    if (tid < 3) {
+        double s = 0.0;
+        if (!skip)
+            for (int l = 0; l < nm; ++l) s += s_t[tid][l];
+        sums[tid] = s;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    const double Fx = sums[0], Fy = sums[1], Mz = sums[2];
+    const double buoy = 1.0 - 1.0 / P->ratio;
+    const double ax = Fx / P->m + buoy * c.grav[0];
+    const double ay = Fy / P->m + buoy * c.grav[1];
+    const double al = Mz / P->I;
+    const double vx = 2.0 / 3.0 * (2.0 * P->V[0] - 0.5 * P->Vm[0] + ax);
+    const double vy = 2.0 / 3.0 * (2.0 * P->V[1] - 0.5 * P->Vm[1] + ay);
+    const double om = 2.0 / 3.0 * (2.0 * P->Om - 0.5 * P->Omm + al);
+    const double nX0 = 2.0 / 3.0 * (2.0 * X0 - 0.5 * P->Xm[0] + vx);
+    const double nX1 = 2.0 / 3.0 * (2.0 * X1 - 0.5 * P->Xm[1] + vy);
+    const double nth = 2.0 / 3.0 * (2.0 * th - 0.5 * P->thm + om);
+    P->Vm[0] = P->V[0];
+    P->Vm[1] = P->V[1];
+    P->Omm = P->Om;
+    P->Xm[0] = X0;
+    P->Xm[1] = X1;
+    P->thm = th;
+    P->V[0] = vx;
+    P->V[1] = vy;
+    P->Om = om;
+    P->X[0] = nX0;
+    P->X[1] = nX1;
+    P->th = nth;
+    P->acc[0] = ax;
+    P->acc[1] = ay;
+    P->alp = al;
+    P->F[0] = Fx;
+    P->F[1] = Fy;
+    P->M = Mz;
+    const long long step = *a.dstep - 1;
+    double* r = a.rec + ((step % kRecSlots) * a.nparts + blockIdx.x) * 10;
+    r[0] = nX0;
+    r[1] = nX1;
+    r[2] = nth;
+    r[3] = vx;
+    r[4] = vy;
+    r[5] = om;
+    r[6] = Fx;
+    r[7] = Fy;
+    r[8] = Mz;
+    r[9] = (double)P->chan;
+    const bool fin = isfinite(vx) && isfinite(vy) && isfinite(om) && isfinite(nX0) &&
+                     isfinite(nX1) && isfinite(nth);
+    if (!fin || skip) {
+        a.flags[0] = 1;
+        atomicMin(&a.flags[1], (int)step);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state, field extraction, population upload.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void initial_velocity(const ChanDev& c, int init, int y, double& ux,
+                                                 double& uy) {
+    ux = 0.0;
+    uy = 0.0;
+    if (init == 1) {
+        double lo = c.uw[2][0], hi = c.uw[3][0];
+        ux = lo + (hi - lo) * (double)y / (double)(c.ny - 1);
+    }
+}
+
+// Writes the post-collision pre-image whose pull gives f^eq(1, u0(x)) at every
+// node: population i at node x holds f^eq_i(1, u0(x + e_i)).
+template <int ST>
+__global__ void init_kernel(StepArgs a, int chan, int init) {
+    const ChanDev c = a.chan[chan];
+    const long long n = (long long)c.nx * c.ny;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(t % c.nx), y = (int)(t / c.nx);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int ys = y + ey(i);
+            if (c.bcy == 0) ys = ys < 0 ? ys + c.ny : (ys >= c.ny ? ys - c.ny : ys);
+            else if (ys < 0 || ys >= c.ny) ys = y;
+            double ux, uy;
+            initial_velocity(c, init, ys, ux, uy);
+            const double exi = (double)ex(i), eyi = (double)ey(i);
+            const double usq = ux * ux + uy * uy;
+            const double eu = exi * ux + eyi * uy;
+            const long long k = pidx(c, i, y, x);
+            if constexpr (ST == ST_F64) {
+                const double rho = 1.0;
+                ((double*)a.fout)[k] = wd(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+            } else {
+                const double dev = wd(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+                store_dev<ST>((typename Sto<ST>::T*)a.fout, k, i, (float)dev, c);
+            }
+        }
+    }
+}
+
+template <int ST>
+__global__ void fields_kernel(StepArgs a, int chan, double* fo, double* rho_o, double* ux_o,
+                              double* uy_o) {
+    const ChanDev c = a.chan[chan];
+    const long long n = (long long)c.nx * c.ny;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(t % c.nx), y = (int)(t / c.nx);
+        double f[9], rho, jx, jy;
+        pull_node_f64<ST>(a.fin, c, x, y, f);
+        moments_f64(f, c, rho, jx, jy);
+        if (fo)
+            for (int i = 0; i < 9; ++i) fo[i * n + t] = f[i];
+        if (rho_o) rho_o[t] = rho;
+        if (ux_o) ux_o[t] = jx / rho;
+        if (uy_o) uy_o[t] = jy / rho;
+    }
+}
+
+// Inverse of the pull: population i at node x takes f_i(x + e_i).
+template <int ST>
+__global__ void set_pop_kernel(StepArgs a, int chan, const double* fi) {
+    const ChanDev c = a.chan[chan];
+    const long long n = (long long)c.nx * c.ny;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(t % c.nx), y = (int)(t / c.nx);
+        for (int i = 0; i < 9; ++i) {
+            int xd = x + ex(i), yd = y + ey(i);
+            if (c.bcx == 0) xd = xd < 0 ? xd + c.nx : (xd >= c.nx ? xd - c.nx : xd);
+            else if (xd < 0 || xd >= c.nx) xd = x;
+            if (c.bcy == 0) yd = yd < 0 ? yd + c.ny : (yd >= c.ny ? yd - c.ny : yd);
+            else if (yd < 0 || yd >= c.ny) yd = y;
+            const double v = fi[i * n + (long long)yd * c.nx + xd];
+            const long long k = pidx(c, i, y, x);
+            if constexpr (ST == ST_F64) {
+                ((double*)a.fout)[k] = v;
+            } else {
+                store_dev<ST>((typename Sto<ST>::T*)a.fout, k, i, (float)(v - wd(i)), c);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+size_t ibm_lds_bytes(int max_cells) { return sizeof(unsigned long long) * max_cells; }
+
+#define LBM_DISPATCH(store, F)                     \
+    switch (store) {                               \
+        case ST_F64: F(ST_F64); break;             \
+        case ST_F32: F(ST_F32); break;             \
+        default: F(ST_F16S); break;                \
+    }
+
+static int grid_for(long long n, int block) {
+    long long g = (n + block - 1) / block;
+    return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx, int ny,
+                       hipStream_t s) {
+    const int grid = grid_for((long long)nx * ny, 256);
+#define L_(ST) init_kernel<ST><<<grid, 256, 0, s>>>(a, chan, init)
+    LBM_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
+size_t ibm_static_lds_bytes() {
+    return 3 * sizeof(double) * kIbmThreads + sizeof(double2) * kIbmThreads + sizeof(int2) * kRound + 64;
+}
+
+hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s) {
+    const int grid = a.nparts > 0 ? a.nparts : 1;
+    const size_t lds = ibm_lds_bytes(a.max_cells);
+    if (lds > 65536) {
+        hipError_t e = hipSuccess;
+#define A_(ST) e = hipFuncSetAttribute((const void*)ibm_force_kernel<ST>, \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+        LBM_DISPATCH(store, A_)
+#undef A_
+        if (e != hipSuccess) return e;
+    }
+#define L_(ST) ibm_force_kernel<ST><<<grid, kIbmThreads, lds, s>>>(a)
+    LBM_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t lattice_dispatch(const StepArgs& a, int tile_w, int npt, int grid,
+                                   hipStream_t s) {
+#define LK(TW, NPT) lattice_kernel<ST, TW, NPT><<<grid, 256, 0, s>>>(a)
+    if (tile_w == 64) {
+        if (npt == 1) LK(64, 1);
+        else if (npt == 2) LK(64, 2);
+        else LK(64, 4);
+    } else if (tile_w == 128) {
+        if (npt == 1) LK(128, 1);
+        else if (npt == 2) LK(128, 2);
+        else LK(128, 4);
+    } else {
+        if (npt == 1) LK(256, 1);
+        else if (npt == 2) LK(256, 2);
+        else LK(256, 4);
+    }
+#undef LK
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hipStream_t s) {
+    int grid = a.persistent > 0 ? (a.persistent < a.ntiles ? a.persistent : a.ntiles) : a.ntiles;
+    if (a.xcd_remap && a.persistent <= 0) grid = (a.ntiles + 7) / 8 * 8;
+    if (grid <= 0) return hipSuccess;
+    switch (store) {
+        case ST_F64: return lattice_dispatch<ST_F64>(a, tile_w, npt, grid, s);
+        case ST_F32: return lattice_dispatch<ST_F32>(a, tile_w, npt, grid, s);
+        default: return lattice_dispatch<ST_F16S>(a, tile_w, npt, grid, s);
+    }
+}
+
+hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s) {
+    if (a.nparts <= 0) return hipSuccess;
+#define L_(ST) traction_kernel<ST><<<a.nparts, kIbmThreads, 0, s>>>(a)
+    LBM_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int store, const StepArgs& a, int chan, int nx, int ny, double* f_out,
+                         double* rho, double* ux, double* uy, hipStream_t s) {
+    const int grid = grid_for((long long)nx * ny, 256);
+#define L_(ST) fields_kernel<ST><<<grid, 256, 0, s>>>(a, chan, f_out, rho, ux, uy)
+    LBM_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
+hipError_t launch_set_pop(int store, const StepArgs& a, int chan, int nx, int ny,
+                          const double* f_in, hipStream_t s) {
+    const int grid = grid_for((long long)nx * ny, 256);
+#define L_(ST) set_pop_kernel<ST><<<grid, 256, 0, s>>>(a, chan, f_in)
+    LBM_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
+}  // namespace lbmk

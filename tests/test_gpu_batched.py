@@ -1,0 +1,99 @@
+"""Batched form: many uneven channels advanced by single launches per kernel
+phase.  Each channel must equal the same channel run alone, bit for bit, and
+the oracle within the FP64 bar; full-size workloads are checked on sampled
+outputs."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs as C
+from workloads import shapes
+
+from gpu_util import body_size, run_gpu, run_oracle, series_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_ensemble(storage, n=6):
+    wl = C.ensemble(storage=storage, n_channels=n, seed=99)
+    # shrink to test sizes: keep the particle, scale the channel to H = 48..96
+    chans = []
+    rng = np.random.default_rng(5)
+    for k, (cfg, parts) in enumerate(wl.channels):
+        H = int(rng.choice([32, 40, 48, 56]))
+        c = C.couette_config(4 * H + k, H, storage=storage)  # ragged widths
+        sh = C.random_shape(rng, 0.25 * H)
+        rb = shapes.bounding_radius(sh)
+        y = float(np.clip(rng.uniform(0.2, 0.8) * (H - 1), rb + 6, H - 1 - rb - 6))
+        chans.append((c, [C.particle(sh, rng.uniform(0, 4 * H), y, rng.uniform(0, 6.28))]))
+    chans.append((C.couette_config(70, 20, storage=storage), []))  # a channel with no particle
+    return chans
+
+
+@pytest.mark.parametrize("storage", [C.STORE_F32, C.STORE_F16S, C.STORE_F64])
+def test_batched_equals_each_channel_alone(storage):
+    chans = _small_ensemble(storage)
+    s, g = run_gpu(chans, 200)
+    s.close()
+    pid = 0
+    for cfg, parts in chans:
+        if not parts:
+            continue
+        s1, g1 = run_gpu([(cfg, parts)], 200)
+        s1.close()
+        # identical except the channel-index column of the record
+        assert np.array_equal(g[:, pid, :9], g1[:, 0, :9])
+        assert np.all(g[:, pid, 9] == chans.index((cfg, parts)))
+        pid += 1
+
+
+def test_batched_fp64_matches_oracle():
+    chans = _small_ensemble(C.STORE_F64, n=4)
+    s, g = run_gpu(chans, 300)
+    s.close()
+    pid = 0
+    for cfg, parts in chans:
+        if not parts:
+            continue
+        _, r = run_oracle(cfg, parts, 300)
+        e = series_errors(g[:, pid], r[:, 0], body_size(parts[0]))
+        assert max(e.values()) < 1e-12, e
+        pid += 1
+
+
+def test_batched_persistent_grid_bitwise():
+    chans = _small_ensemble(C.STORE_F32)
+    _, a = run_gpu(chans, 120)
+    _, b = run_gpu(chans, 120, tuning=dict(persistent_wgs=64, tile_w=128, rows_per_thread=2))
+    assert np.array_equal(a, b)
+
+
+def test_full_ensemble_sampled_channels():
+    """The 256-channel ensemble at full size, in the launch configuration of
+    the benchmark: every particle record is finite, and 4 sampled channels
+    match the oracle over the first 20 steps (FP32 vs FP64 oracle)."""
+    wl = C.ensemble(storage=C.STORE_F32)
+    steps = 20
+    s, g = run_gpu(wl.channels, steps)
+    s.close()
+    assert np.isfinite(g).all()
+    for ch in (0, 77, 150, 255):
+        cfg, parts = wl.channels[ch]
+        _, r = run_oracle(dict(cfg, storage=C.STORE_F64), parts, steps)
+        e_pos = np.abs(g[:, ch, 0:2] - r[:, 0, 0:2]).max() / (cfg["ny"] - 1)
+        assert e_pos < 1e-6, (ch, e_pos)
+        assert np.abs(g[:, ch, 9] - ch).max() == 0
+
+
+def test_full_large_domain_sampled_steps():
+    """4096 x 1024 with 64 particles (FP32): 3 steps against the oracle,
+    every particle."""
+    wl = C.large(storage=C.STORE_F32)
+    cfg, parts = wl.channels[0]
+    steps = 3
+    s, g = run_gpu(wl.channels, steps)
+    s.close()
+    _, r = run_oracle(dict(cfg, storage=C.STORE_F64), parts, steps)
+    e_pos = np.abs(g[..., 0:2] - r[..., 0:2]).max()
+    e_F = np.abs(g[..., 6:8] - r[..., 6:8]).max() / np.abs(r[..., 6:8]).max()
+    assert e_pos < 1e-8 and e_F < 1e-4, (e_pos, e_F)

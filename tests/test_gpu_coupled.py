@@ -1,0 +1,172 @@
+"""GPU coupled step (lattice + MLS-IBM + surface stress + BDF2) vs the oracle.
+
+Comparison metric: for every series of the particle record (x, y, theta, u,
+v, omega, Fx, Fy, M) the largest absolute difference over the run, divided by
+the natural scale of its group in the oracle run (largest displacement for
+x, y; displacement / size for theta; largest speed for u, v; speed / size for
+omega; largest force for Fx, Fy; force x size for M).  Dividing a series by
+its own maximum would make symmetric-zero series (e.g. the sideways motion of
+a sedimenting circle) pure rounding noise.
+
+FP64 bar: 1e-12 on flows whose density deviations are not tiny (the Couette
+cases).  For a fluid essentially at rest (the sedimentation case, |rho - 1|
+of order 1e-7) the marker pressure c_s^2 (rho - 1) is computed from a density
+near 1 held to ~1.1e-16 absolute, so a one-ulp difference of a single
+population (the two sides round exp/cos/sin differently) moves a force by
+~1e-10 of itself; the bar there is 1e-9 for forces and 1e-10 for kinematics.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs as C
+from workloads import shapes
+
+from gpu_util import body_size, run_gpu, run_oracle, series_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(wl_channels, steps, storage=None, tuning=None):
+    s, g = run_gpu(wl_channels, steps, storage=storage, tuning=tuning)
+    errs = []
+    pid = 0
+    for cfg, parts in wl_channels:
+        cfg = dict(cfg)
+        if storage is not None:
+            cfg["storage"] = storage
+        _, r = run_oracle(cfg, parts, steps)
+        for k, p in enumerate(parts):
+            errs.append(series_errors(g[:, pid + k], r[:, k], body_size(p)))
+        pid += len(parts)
+    s.close()
+    return errs
+
+
+def test_couette_fp64_parity():
+    wl = C.couette(storage=C.STORE_F64)
+    errs = _compare(wl.channels, 2000)[0]
+    print({k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-12, errs
+
+
+def test_sedimentation_fp64_parity():
+    wl = C.sedimentation()
+    errs = _compare(wl.channels, 2000)[0]
+    print({k: f"{v:.2e}" for k, v in errs.items()})
+    for k in ("x", "y", "theta", "u", "v", "omega"):
+        assert errs[k] < 1e-10, (k, errs)
+    for k in ("Fx", "Fy", "M"):
+        assert errs[k] < 1e-9, (k, errs)
+
+
+def test_particle_across_periodic_edge_fp64():
+    """A particle straddling x = 0 of a periodic channel: stencils, probes and
+    the force patch wrap."""
+    cfg = C.couette_config(90, 40, storage=C.STORE_F64)
+    sh = shapes.ellipse(12.0, 2.0, n_markers=36)
+    p = C.particle(sh, 1.3, 13.0, 0.7, u=-0.02)
+    errs = _compare([(cfg, [p])], 600)[0]
+    assert max(errs.values()) < 1e-12, errs
+
+
+def test_three_particles_with_overlapping_patches_fp64():
+    cfg = C.couette_config(120, 60, storage=C.STORE_F64)
+    a = C.particle(shapes.circle(10.0, n_markers=32), 40.2, 30.1, 0.0)
+    b = C.particle(shapes.square(9.0), 53.7, 31.4, 0.3)       # patch overlaps a's
+    c = C.particle(shapes.triangle(10.0), 90.0, 22.0, 1.0)
+    errs = _compare([(cfg, [a, b, c])], 400)
+    for e in errs:
+        assert max(e.values()) < 1e-11, errs
+
+
+@pytest.mark.parametrize("fam", ["square", "triangle", "rectangle"])
+def test_polygon_shapes_fp64(fam):
+    cfg = C.couette_config(100, 48, storage=C.STORE_F64)
+    sh = shapes.make(fam, 14.0, aspect_ratio=3.0)
+    errs = _compare([(cfg, [C.particle(sh, 50.0, 21.3, 0.4)])], 500)[0]
+    assert max(errs.values()) < 1e-12, errs
+
+
+def test_dense_markers_fp64():
+    """Markers 0.3 lattice units apart, as in the paper (Sec. 2.1): each node
+    receives force from many markers."""
+    cfg = C.couette_config(80, 40, storage=C.STORE_F64)
+    sh = shapes.circle(10.0, n_markers=105)
+    errs = _compare([(cfg, [C.particle(sh, 40.0, 19.2, 0.0)])], 300)[0]
+    assert max(errs.values()) < 1e-12, errs
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_alternative_kernels_fp64(kernel):
+    """Cubic, quartic and cosine weights (Sec. 2.2, Eqs. (17)-(19))."""
+    cfg = C.couette_config(80, 40, storage=C.STORE_F64, mls_kernel=kernel)
+    sh = shapes.ellipse(14.0, 2.0, n_markers=40)
+    errs = _compare([(cfg, [C.particle(sh, 40.0, 19.2, 0.5)])], 300)[0]
+    assert max(errs.values()) < 1e-12, errs
+
+
+def _traj_errors(g, r, ny):
+    """Trajectory error of a reduced form: positions over the wall gap,
+    angle in radians, angular velocity over the shear rate."""
+    shear = 2 * couette_u(ny) / (ny - 1)
+    e_pos = np.abs(g[..., 0:2] - r[..., 0:2]).max() / (ny - 1)
+    e_th = np.abs(g[..., 2] - r[..., 2]).max()
+    e_om = np.abs(g[..., 5] - r[..., 5]).max() / shear
+    return e_pos, e_th, e_om
+
+
+def couette_u(ny):
+    return C.couette_speed(ny)
+
+
+@pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 1e-4), (C.STORE_F16S, 1e-2)])
+def test_couette_reduced_forms_trajectory_error(storage, tol):
+    wl = C.couette(storage=storage)
+    cfg, parts = wl.channels[0]
+    steps = 5000
+    s, g = run_gpu(wl.channels, steps)
+    s.close()
+    cfg64 = dict(cfg, storage=C.STORE_F64)
+    _, r = run_oracle(cfg64, parts, steps)
+    e = _traj_errors(g, r, cfg["ny"])
+    print(storage, e)
+    assert max(e) < tol, e
+
+
+def test_determinism_and_graph_vs_eager():
+    wl = C.couette(storage=C.STORE_F32)
+    _, a = run_gpu(wl.channels, 301)
+    _, b = run_gpu(wl.channels, 301)
+    _, c = run_gpu(wl.channels, 301, tuning=dict(use_graph=0))
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_checkpoint_restore_replays_bitwise():
+    from paper_1606_01805_amd import Solver
+
+    wl = C.couette(storage=C.STORE_F32)
+    s = Solver(wl.channels)
+    s.step(50)
+    s.checkpoint_save(3)
+    a = s.step(120)
+    pa = s.populations()
+    s.checkpoint_restore(3)
+    b = s.step(120)
+    assert np.array_equal(a, b) and np.array_equal(pa, s.populations())
+
+
+def test_unstable_run_is_reported_at_the_oracle_step():
+    from paper_1606_01805_amd import LBMError, Solver
+
+    cfg = C.base_config(40, 24, tau=0.51, bc_y=1)
+    p = C.particle(shapes.circle(6.0, n_markers=20), 20.0, 12.0, 0.0, 1.0, u=5.0)
+    s = Solver([(cfg, [p])])
+    with pytest.raises(LBMError, match="LBM_EUNSTABLE.*step 2 "):
+        s.step(100)
+    o = oracle.Oracle(cfg)
+    o.add_particle(p)
+    with pytest.raises(FloatingPointError, match="step 2"):
+        o.step(100)

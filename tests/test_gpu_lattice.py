@@ -1,0 +1,129 @@
+"""GPU lattice pass vs the oracle (Sec. 1.1): the FP64 form performs the same
+IEEE operations as the oracle and must match it bit for bit; the reduced
+forms within their storage precision."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs as C
+
+from gpu_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+RNG = np.random.default_rng(42)
+
+
+def _lattice_pair(cfg, steps, f=None, storage=None, tuning=None):
+    from paper_1606_01805_amd import Solver
+
+    s = Solver([(cfg, [])], storage=storage, tuning=tuning)
+    o = oracle.Oracle(cfg)
+    if f is not None:
+        s.set_populations(f)
+        o.set_populations(f)
+    s.step(steps, record=False)
+    o.step(steps, record=False)
+    a, b = s.populations(), o.populations()
+    s.close()
+    return a, b
+
+
+def _noisy(ny, nx, amp=0.05):
+    _, w = oracle.lattice()
+    return w[:, None, None] * (1 + amp * RNG.standard_normal((9, ny, nx)))
+
+
+@pytest.mark.parametrize("nx,ny", [(70, 37), (3, 3), (64, 4), (257, 9)])
+def test_periodic_box_bitwise(nx, ny):
+    cfg = C.base_config(nx, ny, tau=0.9, body_force=[1e-5, -2e-6])
+    a, b = _lattice_pair(cfg, 25, _noisy(ny, nx))
+    assert np.array_equal(a, b)
+
+
+def test_couette_bitwise():
+    a, b = _lattice_pair(C.couette_config(100, 33), 200)
+    assert np.array_equal(a, b)
+
+
+def test_couette_from_rest_bitwise():
+    cfg = C.couette_config(65, 17, tau=0.8)
+    cfg["init"] = 0
+    a, b = _lattice_pair(cfg, 500)
+    assert np.array_equal(a, b)
+
+
+def test_poiseuille_bitwise():
+    a, b = _lattice_pair(C.base_config(40, 17, tau=0.8, bc_y=1, body_force=[1e-6, 0.0]), 300)
+    assert np.array_equal(a, b)
+
+
+def test_side_walls_bitwise():
+    cfg = C.base_config(19, 30, tau=0.7, bc_x=1, body_force=[0.0, 2e-6],
+                        u_wall=[[0.0, 0.01], [0.0, -0.02], [0, 0], [0, 0]])
+    a, b = _lattice_pair(cfg, 300)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("tile_w,npt,pers", [(64, 1, 0), (128, 2, 0), (256, 4, 0), (64, 4, 7), (256, 1, 3)])
+def test_launch_shapes_do_not_change_results(tile_w, npt, pers):
+    cfg = C.base_config(130, 45, tau=0.8, bc_y=1, body_force=[1e-6, 0.0])
+    f = None
+    a, _ = _lattice_pair(cfg, 40, f, tuning=dict(tile_w=tile_w, rows_per_thread=npt, persistent_wgs=pers))
+    b, _ = _lattice_pair(cfg, 40, f)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 2e-8), (C.STORE_F16S, 3e-5)])
+def test_reduced_forms_on_couette(storage, tol):
+    """FP32 / FP16S storage of f - w_i with FP32 arithmetic: fields stay
+    within the storage precision of the FP64 reference."""
+    cfg = C.couette_config(100, 33)
+    a, b = _lattice_pair(cfg, 300, storage=storage)
+    assert np.abs(a - b).max() < tol
+
+
+@pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 1e-4), (C.STORE_F16S, 5e-2)])
+def test_poiseuille_reduced(storage, tol):
+    """Force-driven Poiseuille at u_max ~ 0.03 (the Mach range of the Couette
+    workloads): relative error of the steady profile.  Each collision rounds
+    the stored deviation d ~ w (3 e.u) ~ 1e-2 to its storage precision (2^-24
+    in FP32, 2^-11 in FP16); the slowest viscous mode relaxes at nu k^2 ~ 4e-3
+    per step (k = pi / 16), so the steady profile may sit ~ulp(d) / (nu k^2)
+    away from the exact one: ~1e-5 (FP32) and ~3e-2 (FP16) of u_max."""
+    ny, tau, g = 17, 0.8, 1e-4
+    nu = (tau - 0.5) / 3
+    from paper_1606_01805_amd import Solver
+
+    s = Solver([(C.base_config(8, ny, tau=tau, bc_y=1, body_force=[g, 0.0]), [])], storage=storage)
+    s.step(20000, record=False)
+    _, ux, _ = s.fields()
+    y = np.arange(ny)
+    exact = g / (2 * nu) * y * (ny - 1 - y)
+    err = np.abs(ux - exact[:, None]).max() / exact.max()
+    print(storage, err)
+    assert err < tol
+
+
+def test_set_get_populations_roundtrip():
+    from paper_1606_01805_amd import Solver
+
+    cfg = C.base_config(33, 20)
+    f = _noisy(20, 33)
+    for st, tol in ((C.STORE_F64, 0.0), (C.STORE_F32, 1e-8), (C.STORE_F16S, 2e-5)):
+        s = Solver([(cfg, [])], storage=st)
+        s.set_populations(f)
+        assert np.abs(s.populations() - f).max() <= tol
+        s.close()
+
+
+def test_fields_match_oracle_definition():
+    cfg = C.couette_config(50, 21, body_force=[1e-5, 0.0])
+    cfg["bc_x"] = 0
+    from paper_1606_01805_amd import Solver
+
+    s = Solver([(cfg, [])])
+    o = oracle.Oracle(cfg)
+    s.step(30, record=False)
+    o.step(30, record=False)
+    for a, b in zip(s.fields(), o.fields()):
+        assert np.array_equal(a, b)

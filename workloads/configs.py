@@ -38,7 +38,7 @@ STORE_F64, STORE_F32, STORE_F16S = 0, 1, 2
 def base_config(nx, ny, tau=1.0, **kw):
     c = dict(nx=int(nx), ny=int(ny), tau=float(tau), bc_x=PERIODIC, bc_y=PERIODIC,
              u_wall=[[0.0, 0.0] for _ in range(4)], init=INIT_REST, body_force=[0.0, 0.0],
-             gravity=[0.0, 0.0], storage=STORE_F64, fp16_exp=10, mls_rw=2.6, mls_alpha=0.3,
+             gravity=[0.0, 0.0], storage=STORE_F64, fp16_exp=14, mls_rw=2.6, mls_alpha=0.3,
              probe_dn=1.2, mls_kernel=0, spread_scale=0)
     c.update(kw)
     return c
