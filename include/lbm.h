@@ -118,6 +118,9 @@ typedef struct lbm_tuning {
     int32_t xcd_remap;       /* 1: hand each of the 8 XCDs (one L2 each) a
                                 contiguous block of tiles, so tiles that share
                                 halo cache lines run under the same L2 */
+    int32_t overlap;         /* 1: run the surface-stress / rigid-body kernel
+                                on a second stream, concurrently with the
+                                lattice pass (both need only the force stage) */
 } lbm_tuning;
 
 typedef struct lbm_handle lbm_handle;

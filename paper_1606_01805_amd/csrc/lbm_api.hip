@@ -5,6 +5,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,6 +46,8 @@ struct lbm_handle {
     int store = 0;
     size_t elem = 8;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;    // second stream for the particle kernel
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void* buf[2] = {nullptr, nullptr};
     void* ws_alloc = nullptr;
     size_t buf_bytes = 0;
@@ -52,7 +55,7 @@ struct lbm_handle {
     ChanDev* dchan = nullptr;
     std::vector<TileDev> htiles;
     TileDev* dtiles = nullptr;
-    lbm_tuning tune{256, 1, 0, 1, 1};
+    lbm_tuning tune{256, 1, 0, 1, 1, 0};
     bool tiles_dirty = true;
     std::vector<PartHost> parts;
     std::vector<int> dev_of_user;  // user particle id -> device index
@@ -65,7 +68,7 @@ struct lbm_handle {
     double2* dcontrib = nullptr;
     double* dmscr = nullptr;
     int* dflags = nullptr;
-    int* dtflag = nullptr;
+    int* dtlist = nullptr;
     long long* dstep = nullptr;
     double* drec = nullptr;
     int nparts = 0;
@@ -132,9 +135,16 @@ static int validate_cfg(const lbm_channel_config& c, int idx) {
 
 static size_t pitch_of(int nx) { return round_up((size_t)nx, 64); }
 
+static size_t plane_pad() {
+    const char* v = getenv("LBM_PLANE_PAD");
+    return v ? (size_t)atol(v) : 0;
+}
+
+static size_t plane_of(const lbm_channel_config& c) { return (size_t)c.ny * pitch_of(c.nx) + plane_pad(); }
+
 static size_t buffer_bytes(const lbm_channel_config* cfg, int n, size_t elem) {
     size_t e = 0;
-    for (int i = 0; i < n; ++i) e += 9 * (size_t)cfg[i].ny * pitch_of(cfg[i].nx);
+    for (int i = 0; i < n; ++i) e += 9 * plane_of(cfg[i]);
     return round_up(e * elem, 4096);
 }
 
@@ -150,7 +160,7 @@ extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) 
 static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     StepArgs a{};
     a.parity = parity < 0 ? cur : parity;
-    a.tflag = h->dtflag;
+    a.tlist = h->dtlist;
     a.tile_w = h->tune.tile_w;
     a.tile_h = (256 / h->tune.tile_w) * h->tune.rows_per_thread;
     a.fin = h->buf[cur];
@@ -194,14 +204,14 @@ static int build_tiles(lbm_handle* h) {
             for (int x0 = 0; x0 < h->cfg[c].nx; x0 += tw) h->htiles.push_back(TileDev{c, x0, y0, 0});
     }
     if (h->dtiles) (void)hipFree(h->dtiles);
-    if (h->dtflag) (void)hipFree(h->dtflag);
+    if (h->dtlist) (void)hipFree(h->dtlist);
     h->dtiles = nullptr;
-    h->dtflag = nullptr;
+    h->dtlist = nullptr;
     const size_t nt = h->htiles.size();
     HIPCHK(h, hipMalloc(&h->dtiles, sizeof(TileDev) * nt));
     HIPCHK(h, hipMemcpy(h->dtiles, h->htiles.data(), sizeof(TileDev) * nt, hipMemcpyHostToDevice));
-    HIPCHK(h, hipMalloc(&h->dtflag, sizeof(int) * 2 * nt));
-    HIPCHK(h, hipMemset(h->dtflag, 0, sizeof(int) * 2 * nt));
+    HIPCHK(h, hipMalloc(&h->dtlist, sizeof(int) * 2 * nt * kTileList));
+    HIPCHK(h, hipMemset(h->dtlist, 0, sizeof(int) * 2 * nt * kTileList));
     HIPCHK(h, hipMemcpy(h->dchan, h->hchan.data(), sizeof(ChanDev) * h->hchan.size(), hipMemcpyHostToDevice));
     h->tiles_dirty = false;
     drop_graphs(h);
@@ -218,7 +228,7 @@ static void fill_chan(ChanDev& d, const lbm_channel_config& c, long long off) {
     d.kernel = c.mls_kernel;
     d.spread_unit = c.spread_scale == LBM_SPREAD_UNIT;
     d.off = off;
-    d.plane = (long long)c.ny * d.pitch;
+    d.plane = (long long)plane_of(c);
     d.tau = c.tau;
     d.nu = (c.tau - 0.5) / 3.0;
     for (int s = 0; s < 4; ++s)
@@ -297,7 +307,7 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
     h->hchan.resize(n);
     for (int i = 0; i < n; ++i) {
         fill_chan(h->hchan[i], cfg[i], off);
-        off += 9LL * cfg[i].ny * (long long)pitch_of(cfg[i].nx);
+        off += 9LL * (long long)plane_of(cfg[i]);
     }
     int r;
     if (hipMalloc(&h->dchan, sizeof(ChanDev) * n) != hipSuccess ||
@@ -315,6 +325,12 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
     if (hipMemcpy(h->dflags, fl, sizeof(fl), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->dstep, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
         h->err = "upload of flags failed";
+        return fail_init(LBM_EDEVICE);
+    }
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+        h->err = "creating the particle stream or its events failed";
         return fail_init(LBM_EDEVICE);
     }
     if ((r = build_tiles(h)) != LBM_OK) return fail_init(r);
@@ -363,6 +379,8 @@ extern "C" int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_partic
         FAIL(h, LBM_EINVAL, "particle closer than 3 nodes to a wall");
     if (c.bc_y == LBM_BC_PERIODIC && (d->y < -1e6 || d->y > 1e6)) FAIL(h, LBM_EINVAL, "position out of range");
     if (c.bc_x == LBM_BC_PERIODIC && (d->x < -1e6 || d->x > 1e6)) FAIL(h, LBM_EINVAL, "position out of range");
+    // the force patch spans the anchors of [X - rb, X + rb] plus one node of
+    // stencil on each side: at most ceil(2 rb) + 4 nodes per axis
     const int side = (int)std::ceil(2.0 * rb) + 6;
     if (side > c.nx || side > c.ny) FAIL(h, LBM_EINVAL, "particle wider than the channel");
     if ((long long)side * side > h->max_cells)
@@ -405,6 +423,7 @@ static int finalize(lbm_handle* h) {
         q.V[1] = q.Vm[1] = P.d.v;
         q.Om = q.Omm = P.d.omega;
         q.ratio = P.d.density_ratio;
+        q.rb = P.rb;
         q.m = P.d.density_ratio * P.d.area;
         q.I = P.d.density_ratio * P.d.polar_moment;
         q.chan = P.chan;
@@ -447,8 +466,19 @@ static int finalize(lbm_handle* h) {
 static int enqueue_step(lbm_handle* h, int cur) {
     StepArgs a = make_args(h, cur);
     HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-    HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
-    HIPCHK(h, launch_traction(h->store, a, h->stream));
+    if (h->tune.overlap && h->nparts > 0 && h->side) {
+        // fork: the surface-stress kernel reads the force patches and the
+        // previous populations only, so it runs beside the lattice pass
+        HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
+        HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        HIPCHK(h, launch_traction(h->store, a, h->side));
+        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+        HIPCHK(h, hipEventRecord(h->ev_join, h->side));
+        HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+    } else {
+        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+        HIPCHK(h, launch_traction(h->store, a, h->stream));
+    }
     return LBM_OK;
 }
 
@@ -647,6 +677,7 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
     if (t->persistent_wgs < 0) FAIL(h, LBM_EINVAL, "persistent_wgs must be >= 0");
     if (t->use_graph != 0 && t->use_graph != 1) FAIL(h, LBM_EINVAL, "use_graph must be 0 or 1");
     if (t->xcd_remap != 0 && t->xcd_remap != 1) FAIL(h, LBM_EINVAL, "xcd_remap must be 0 or 1");
+    if (t->overlap != 0 && t->overlap != 1) FAIL(h, LBM_EINVAL, "overlap must be 0 or 1");
     const bool tiles = t->tile_w != h->tune.tile_w || t->rows_per_thread != h->tune.rows_per_thread;
     h->tune = *t;
     if (tiles) h->tiles_dirty = true;
@@ -669,7 +700,9 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
     const int par0 = h->cur;
-    for (int k = 0; k < 3; ++k) {
+    const int order[3] = {1, 0, 2};  // lattice first: repeated force launches refill the tile lists
+    for (int kk = 0; kk < 3; ++kk) {
+        const int k = order[kk];
         HIPCHK(h, hipEventRecord(e0, h->stream));
         for (int i = 0; i < reps; ++i) {
             StepArgs a = make_args(h, h->cur, par0);
@@ -699,8 +732,12 @@ extern "C" const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c
 extern "C" int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;
     drop_graphs(h);
+    if (h->side) (void)hipStreamSynchronize(h->side);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     void* ptrs[] = {h->ws_alloc, h->dchan, h->dtiles, h->dparts, h->dxi, h->dnrm, h->dds, h->dpatch,
-                    h->dcontrib, h->dmscr, h->dflags, h->dtflag, h->dstep, h->drec};
+                    h->dcontrib, h->dmscr, h->dflags, h->dtlist, h->dstep, h->drec};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& c : h->ck) {

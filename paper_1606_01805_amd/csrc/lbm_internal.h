@@ -11,6 +11,7 @@ constexpr int kMaxCellsDefault = 8192;   // force-patch cells of one particle (r
 constexpr int kChunk = 32;               // markers per spreading chunk (one u32 mask)
 constexpr int kRecSlots = 1024;          // trajectory ring-buffer depth (steps)
 constexpr int kMaxNeighbours = 8;        // short candidate lists of force patches
+constexpr int kTileList = 8;             // per-tile list: count + 7 particle indices
 constexpr int kRound = 64;               // markers per round of the particle kernels
 constexpr int kIbmThreads = 9 * kRound;  // one thread per (marker, stencil node)
 
@@ -47,6 +48,7 @@ struct PartDev {
     double acc[2], alp;      // accelerations of the previous step
     double F[2], M;          // force and moment of the last step
     double m, I, ratio;
+    double rb;               // largest marker distance from the centroid
     int chan, mbeg, nm, patch_cap;
     int bx0, by0, bw, bh;    // patch box in unwrapped lattice coordinates
     long long patch_off;     // first cell of the patch in the patch pool
@@ -73,8 +75,8 @@ struct StepArgs {
     long long* dstep;        // steps started so far
     double* rec;             // [kRecSlots][nparts][10]
     int max_cells;           // LDS mask capacity of the spreading kernel
-    int* tflag;              // [2][ntiles] tiles touched by a force patch
-    int parity;              // which half of tflag this step sets / reads
+    int* tlist;              // [2][ntiles][kTileList] particles whose patches touch a tile
+    int parity;              // which half of tlist this step fills / reads
     int tile_w, tile_h;      // tile extent in nodes
 };
 

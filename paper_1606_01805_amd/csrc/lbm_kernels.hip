@@ -51,23 +51,72 @@ __device__ __forceinline__ long long pidx(const ChanDev& c, int i, int y, int x)
     return c.off + (long long)i * c.plane + (long long)y * c.pitch + x;
 }
 
-// Source node of population i for a pull at (x, y); false when it lies beyond
-// a wall (the population is then reconstructed by the wall condition).
-__device__ __forceinline__ bool pull_src(const ChanDev& c, int i, int x, int y, int& xs, int& ys) {
-    xs = x - ex(i);
-    ys = y - ey(i);
-    bool ok = true;
-    if (c.bcx == 0) {
-        xs = xs < 0 ? xs + c.nx : (xs >= c.nx ? xs - c.nx : xs);
-    } else if (xs < 0 || xs >= c.nx) {
-        ok = false;
+// Source node of population i for a pull at (x, y).  Periodic axes wrap.  A
+// source beyond a wall-bounded edge is replaced by the node itself (always a
+// valid address): that population enters through the wall and is
+// overwritten by the wall closure, which reads only the known populations.
+__device__ __forceinline__ int pull_coord(int v, int self, int n, bool periodic) {
+    const int lo = v < 0, hi = v >= n;
+    return periodic ? v + (lo - hi) * n : ((lo | hi) ? self : v);
+}
+
+__device__ __forceinline__ void pull_src(const ChanDev& c, int i, int x, int y, int& xs, int& ys) {
+    xs = pull_coord(x - ex(i), x, c.nx, c.bcx == 0);
+    ys = pull_coord(y - ey(i), y, c.ny, c.bcy == 0);
+}
+
+// Wave-uniform copies (scalar registers) of values every lane holds alike.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ long long uni(long long v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double(uni(__double_as_longlong(v))); }
+
+// The channel descriptor a whole workgroup works on, in scalar registers:
+// branches on the boundary kinds stay uniform.
+__device__ __forceinline__ ChanDev load_chan(const ChanDev* p) {
+    ChanDev c;
+    c.nx = uni(p->nx);
+    c.ny = uni(p->ny);
+    c.pitch = uni(p->pitch);
+    c.bcx = uni(p->bcx);
+    c.bcy = uni(p->bcy);
+    c.p_begin = uni(p->p_begin);
+    c.p_end = uni(p->p_end);
+    c.kernel = uni(p->kernel);
+    c.spread_unit = uni(p->spread_unit);
+    c.pad0 = 0;
+    c.off = uni(p->off);
+    c.plane = uni(p->plane);
+    c.tau = uni(p->tau);
+    c.nu = uni(p->nu);
+    for (int s = 0; s < 4; ++s)
+        for (int k = 0; k < 2; ++k) {
+            c.uw[s][k] = uni(p->uw[s][k]);
+            c.f_uw[s][k] = uni(p->f_uw[s][k]);
+        }
+    for (int k = 0; k < 2; ++k) {
+        c.g[k] = uni(p->g[k]);
+        c.grav[k] = uni(p->grav[k]);
+        c.f_g[k] = uni(p->f_g[k]);
     }
-    if (c.bcy == 0) {
-        ys = ys < 0 ? ys + c.ny : (ys >= c.ny ? ys - c.ny : ys);
-    } else if (ys < 0 || ys >= c.ny) {
-        ok = false;
+    c.rw = uni(p->rw);
+    c.alpha = uni(p->alpha);
+    c.dn = uni(p->dn);
+    c.f_omega = uni(p->f_omega);
+    c.f_pref = uni(p->f_pref);
+    for (int k = 0; k < 3; ++k) {
+        c.sc[k] = uni(p->sc[k]);
+        c.isc[k] = uni(p->isc[k]);
     }
-    return ok;
+    c.tile0 = uni(p->tile0);
+    c.tiles_x = uni(p->tiles_x);
+    return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -209,7 +258,8 @@ __device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c,
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int xs, ys;
-            f[i] = pull_src(c, i, x, y, xs, ys) ? p[pidx(c, i, ys, xs)] : 0.0;
+            pull_src(c, i, x, y, xs, ys);
+            f[i] = p[pidx(c, i, ys, xs)];
         }
         walls_f64(c, x, y, f);
     } else {
@@ -219,7 +269,8 @@ __device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c,
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int xs, ys;
-            d[i] = pull_src(c, i, x, y, xs, ys) ? load_dev<ST>(p, pidx(c, i, ys, xs), i, c) : 0.0f;
+            pull_src(c, i, x, y, xs, ys);
+            d[i] = load_dev<ST>(p, pidx(c, i, ys, xs), i, c);
         }
         walls_dev(c, x, y, d);
 #pragma unroll
@@ -414,9 +465,10 @@ __device__ __forceinline__ MlsInv mls_inverse(const ChanDev& c, const double* w,
     return r;
 }
 
-// Mark the lattice tiles that a patch box [x0, x0 + w) x [y0, y0 + h)
-// (unwrapped coordinates) overlaps, so the lattice pass looks up particle
-// forces only there.  Periodic ranges split into at most two pieces.
+// Append this particle to the lists of the lattice tiles that its patch box
+// [x0, x0 + w) x [y0, y0 + h) (unwrapped coordinates) overlaps, so the
+// lattice pass looks up particle forces only there and only for listed
+// particles.  Periodic ranges split into at most two pieces.
 __device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, int x0, int y0,
                                            int w, int h, int tid, int nthr) {
     int xr[2][2], yr[2][2], nxr = 0, nyr = 0;
@@ -438,14 +490,17 @@ __device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, 
     };
     nxr = split(x0, w, c.nx, c.bcx == 0, xr);
     nyr = split(y0, h, c.ny, c.bcy == 0, yr);
-    int* fl = a.tflag + (long long)a.parity * a.ntiles;
+    int* tl = a.tlist + (long long)a.parity * a.ntiles * kTileList;
     for (int p = 0; p < nxr; ++p)
         for (int q = 0; q < nyr; ++q) {
             const int tx0 = xr[p][0] / a.tile_w, tx1 = xr[p][1] / a.tile_w;
             const int ty0 = yr[q][0] / a.tile_h, ty1 = yr[q][1] / a.tile_h;
             const int ntx = tx1 - tx0 + 1, cnt = ntx * (ty1 - ty0 + 1);
-            for (int t = tid; t < cnt; t += nthr)
-                atomicOr(&fl[c.tile0 + (ty0 + t / ntx) * c.tiles_x + tx0 + t % ntx], 1);
+            for (int t = tid; t < cnt; t += nthr) {
+                int* e = tl + (long long)(c.tile0 + (ty0 + t / ntx) * c.tiles_x + tx0 + t % ntx) * kTileList;
+                const int slot = atomicAdd(e, 1);
+                if (slot < kTileList - 1) e[1 + slot] = (int)blockIdx.x;
+            }
         }
 }
 
@@ -455,7 +510,6 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     __shared__ double s_w[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double2 s_con[kIbmThreads];         // c_l phi_k F_l of the round
     __shared__ int2 s_anc[kRound];
-    __shared__ int box[4];  // min i0, min j0, max i0, max j0
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
     if ((int)blockIdx.x >= a.nparts) return;
@@ -477,41 +531,12 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         }
         return;
     }
-    const double cs = cos(th), sn = sin(th);
-    if (tid == 0) {
-        box[0] = box[1] = 0x7fffffff;
-        box[2] = box[3] = -0x7fffffff;
-    }
-    __syncthreads();
-
-    // Bounding box of the marker anchors: the force patch.  Reduced within
-    // each wave first, then one LDS atomic per wave and bound.
-    {
-        int mn0 = 0x7fffffff, mn1 = 0x7fffffff, mx0 = -0x7fffffff, mx1 = -0x7fffffff;
-        for (int l = tid; l < nm; l += blockDim.x) {
-            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
-            mn0 = min(mn0, m.i0);
-            mn1 = min(mn1, m.j0);
-            mx0 = max(mx0, m.i0);
-            mx1 = max(mx1, m.j0);
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            mn0 = min(mn0, __shfl_xor(mn0, o));
-            mn1 = min(mn1, __shfl_xor(mn1, o));
-            mx0 = max(mx0, __shfl_xor(mx0, o));
-            mx1 = max(mx1, __shfl_xor(mx1, o));
-        }
-        if ((tid & 63) == 0 && tid < nm) {
-            atomicMin(&box[0], mn0);
-            atomicMin(&box[1], mn1);
-            atomicMax(&box[2], mx0);
-            atomicMax(&box[3], mx1);
-        }
-    }
-    __syncthreads();
-    const int bx0u = box[0] - 1, by0u = box[1] - 1;
-    const long long bwl = (long long)box[2] - box[0] + 3, bhl = (long long)box[3] - box[1] + 3;
-    if (bwl > c.nx || bhl > c.ny || bwl * bhl > P->patch_cap || bwl * bhl > a.max_cells) {
+    // Force patch: a box that holds every possible stencil node of markers
+    // within rb of the centroid (anchors round half up, plus one node).
+    const double rb = P->rb + 1e-6;
+    const int bx0u = (int)floor(X0 - rb + 0.5) - 1, by0u = (int)floor(X1 - rb + 0.5) - 1;
+    const int bw = (int)floor(X0 + rb + 0.5) + 2 - bx0u, bh = (int)floor(X1 + rb + 0.5) + 2 - by0u;
+    if (bw > c.nx || bh > c.ny || (long long)bw * bh > P->patch_cap || (long long)bw * bh > a.max_cells) {
         if (tid == 0) {
             atomicOr(&a.flags[2], 1);
             P->bw = 0;
@@ -519,21 +544,16 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         }
         return;
     }
-    const int bw = (int)bwl, bh = (int)bhl;
     const int ncell = bw * bh;
     double2* patch = a.patch + P->patch_off;
-    for (int k = tid; k < ncell; k += blockDim.x) {
-        patch[k] = make_double2(0.0, 0.0);
-        smask[k] = 0ull;
-    }
-    mark_tiles(a, c, bx0u, by0u, bw, bh, tid, blockDim.x);
+    for (int k = tid; k < ncell; k += blockDim.x) smask[k] = 0ull;
     if (tid == 0) {
         P->bx0 = wrapc(bx0u, c.nx, c.bcx == 0);
         P->by0 = wrapc(by0u, c.ny, c.bcy == 0);
         P->bw = bw;
         P->bh = bh;
     }
-    __syncthreads();
+    const double cs = cos(th), sn = sin(th);
 
     const int lo = tid / 9, k = tid % 9;
     for (int r0 = 0; r0 < nm; r0 += kRound) {
@@ -559,39 +579,45 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
             if (k == 0) s_anc[lo] = make_int2(m.i0, m.j0);
         }
         __syncthreads();
-        // (2) per marker, all in the first wave (thread lm leads marker
-        // r0 + lm): phi, U = sum phi u* (k ascending), F = U_b - U (dt = 1),
-        // contributions; its bit in the mask of its anchor cell
-        if (tid < kRound && r0 + tid < nm) {
-            const int lm = tid, l = r0 + lm;
-            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
-            const int lo = lm;
-            const double* w = s_w + lo * 9;
-            const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, false);
-            double Ux = 0.0, Uy = 0.0;
-            for (int q = 0; q < 9; ++q) {
-                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                if (!node_valid(c, ii, jj)) continue;
-                const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
-                const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
-                Ux += phi * s_ux[lo * 9 + q];
-                Uy += phi * s_uy[lo * 9 + q];
-            }
-            const double ubx = V0 - Om * m.ry;
-            const double uby = V1 + Om * m.rx;
-            const double Fx = ubx - Ux, Fy = uby - Uy;
-            const double cl = c.spread_unit ? 1.0 : a.ds[mb + l];
-            for (int q = 0; q < 9; ++q) {
-                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                double2 v = make_double2(0.0, 0.0);
-                if (node_valid(c, ii, jj)) {
+        if (tid < kRound) {
+            // (2) per marker, all in the first wave (thread lo leads marker
+            // r0 + lo): phi, U = sum phi u* (k ascending), F = U_b - U
+            // (dt = 1), contributions; its bit in the mask of its anchor cell
+            if (r0 + tid < nm) {
+                const int lo = tid, l = r0 + lo;
+                const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+                const double cl = c.spread_unit ? 1.0 : a.ds[mb + l];
+                const double* w = s_w + lo * 9;
+                const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, false);
+                double Ux = 0.0, Uy = 0.0;
+                for (int q = 0; q < 9; ++q) {
+                    const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
+                    if (!node_valid(c, ii, jj)) continue;
                     const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
                     const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
-                    v = make_double2(cl * phi * Fx, cl * phi * Fy);
+                    Ux += phi * s_ux[lo * 9 + q];
+                    Uy += phi * s_uy[lo * 9 + q];
                 }
-                s_con[lo * 9 + q] = v;
+                const double ubx = V0 - Om * m.ry;
+                const double uby = V1 + Om * m.rx;
+                const double Fx = ubx - Ux, Fy = uby - Uy;
+                for (int q = 0; q < 9; ++q) {
+                    const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
+                    double2 v = make_double2(0.0, 0.0);
+                    if (node_valid(c, ii, jj)) {
+                        const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
+                        const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
+                        v = make_double2(cl * phi * Fx, cl * phi * Fy);
+                    }
+                    s_con[lo * 9 + q] = v;
+                }
+                atomicOr(&smask[(m.j0 - by0u) * bw + (m.i0 - bx0u)], 1ull << lo);
             }
-            atomicOr(&smask[(m.j0 - by0u) * bw + (m.i0 - bx0u)], 1ull << lo);
+        } else if (r0 == 0) {
+            // meanwhile the other waves clear the patch and list the tiles it
+            // covers for the lattice pass
+            for (int q = tid - kRound; q < ncell; q += blockDim.x - kRound) patch[q] = make_double2(0.0, 0.0);
+            mark_tiles(a, c, bx0u, by0u, bw, bh, tid - kRound, blockDim.x - kRound);
         }
         __syncthreads();
         // (3) spreading f_lb(x_k) = sum_l c_l phi^l_k F_l: the lowest marker
@@ -638,22 +664,15 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
 // ---------------------------------------------------------------------------
 // Kernel 2: the lattice pass.
 // ---------------------------------------------------------------------------
-// FP64 form, reference expression order.
+// FP64 form, reference expression order.  f holds the pulled populations.
 __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c, int x,
-                                                  int y, const int* list, int nlist) {
-    const double* fin = (const double*)a.fin;
-    double* fout = (double*)a.fout;
-    double f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int xs, ys;
-        f[i] = pull_src(c, i, x, y, xs, ys) ? fin[pidx(c, i, ys, xs)] : 0.0;
-    }
+                                                  int y, double f[9], const int* list, int nlist,
+                                                  double* __restrict__ fout) {
     walls_f64(c, x, y, f);
     double rho, jx, jy;
     moments_f64(f, c, rho, jx, jy);
     double flbx = 0.0, flby = 0.0;
-    if (nlist > kMaxNeighbours) patch_force(a, c, x, y, flbx, flby);
+    if (nlist >= kTileList) patch_force(a, c, x, y, flbx, flby);
     else if (nlist > 0) patch_force_list(a, c, list, nlist, x, y, flbx, flby);
     const double gx = c.g[0], gy = c.g[1];
     const double ux = (jx + 0.5 * flbx) / rho;
@@ -678,26 +697,18 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
     }
 }
 
-// Reduced forms: deviations in FP32.
+// Reduced forms: deviations in FP32.  d holds the pulled deviations.
 template <int ST>
 __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c, int x,
-                                                  int y, const int* list, int nlist) {
-    using T = typename Sto<ST>::T;
-    const T* fin = (const T*)a.fin;
-    T* fout = (T*)a.fout;
-    float d[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int xs, ys;
-        d[i] = pull_src(c, i, x, y, xs, ys) ? load_dev<ST>(fin, pidx(c, i, ys, xs), i, c) : 0.0f;
-    }
+                                                  int y, float d[9], const int* list, int nlist,
+                                                  typename Sto<ST>::T* __restrict__ fout) {
     walls_dev(c, x, y, d);
     const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const float rho = 1.0f + drho;
     float flbx = 0.0f, flby = 0.0f;
     if (nlist > 0) {
         double fx, fy;
-        if (nlist > kMaxNeighbours) patch_force(a, c, x, y, fx, fy);
+        if (nlist >= kTileList) patch_force(a, c, x, y, fx, fy);
         else patch_force_list(a, c, list, nlist, x, y, fx, fy);
         flbx = (float)fx;
         flby = (float)fy;
@@ -727,10 +738,13 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
 
 template <int ST, int TW, int NPT>
 __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
+    using T = typename Sto<ST>::T;
+    const T* __restrict__ fin = (const T*)a.fin;
+    T* __restrict__ fout = (T*)a.fout;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int stride = a.persistent ? (int)gridDim.x : a.ntiles;
-    const int* fl = a.tflag + (long long)a.parity * a.ntiles;
-    int* fl_next = a.tflag + (long long)(1 - a.parity) * a.ntiles;
+    const int* tl_cur = a.tlist + (long long)a.parity * a.ntiles * kTileList;
+    int* tl_next = a.tlist + (long long)(1 - a.parity) * a.ntiles * kTileList;
     // Workgroups are dispatched round-robin over the 8 XCDs.  With the remap
     // (one workgroup per tile, grid rounded up to a multiple of 8) XCD x
     // takes the contiguous tile block [x * per, (x + 1) * per).
@@ -740,31 +754,73 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
         t0 = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     }
     for (int t = t0; t < a.ntiles; t += stride) {
-        const TileDev tl = a.tiles[t];
-        const ChanDev& c = a.chan[tl.chan];
-        const int x = tl.x0 + lx;
-        // force patches touch this tile?  (set by the particle kernel of this
-        // step; the other half is cleared for the next step)  Then list the
-        // channel's particles whose patch boxes overlap the tile.
-        const bool hasf = fl[t] != 0;
-        if (threadIdx.x == 0) fl_next[t] = 0;
+        const TileDev* tp = a.tiles + t;
+        const int tx0 = uni(tp->x0), ty0 = uni(tp->y0);
+        const ChanDev c = load_chan(a.chan + uni(tp->chan));
+        const int x = tx0 + lx;
+        const int xl = x < c.nx ? x : c.nx - 1;  // loads of lanes past the edge stay in bounds
+        // Particles whose force patches overlap this tile, appended by the
+        // particle kernel of this step; sorted ascending and deduplicated so
+        // overlapping patches add in a fixed order.  The other half of the
+        // list store is reset for the next step.
+        const int* e = tl_cur + (long long)t * kTileList;
+        const int cnt = uni(e[0]);
+        if (threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
+        int list[kTileList - 1];
         int nlist = 0;
-        int list[kMaxNeighbours];
-        if (hasf) {
-            for (int q = c.p_begin; q < c.p_end; ++q) {
-                const PartDev& P = a.parts[q];
-                if (P.bw > 0 && boxes_overlap(c, tl.x0, tl.y0, TW, (256 / TW) * NPT, P.bx0, P.by0, P.bw, P.bh)) {
-                    if (nlist < kMaxNeighbours) list[nlist] = q;
-                    ++nlist;
+        if (cnt > kTileList - 1) {
+            nlist = kTileList;  // more patches than slots: scan the channel's particles
+        } else {
+            for (int j = 0; j < cnt; ++j) {
+                const int v = uni(e[1 + j]);
+                int k = nlist;
+                bool dup = false;
+                for (int m = 0; m < nlist; ++m) dup |= list[m] == v;
+                if (dup) continue;
+                while (k > 0 && list[k - 1] > v) {
+                    list[k] = list[k - 1];
+                    --k;
                 }
+                list[k] = v;
+                ++nlist;
             }
         }
+        // all pulls of the thread's rows first, then collide and store
+        if constexpr (ST == ST_F64) {
+            double f[NPT][9];
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) {
-            const int y = tl.y0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) {
-                if constexpr (ST == ST_F64) collide_store_f64(a, c, x, y, list, nlist);
-                else collide_store_dev<ST>(a, c, x, y, list, nlist);
+            for (int r = 0; r < NPT; ++r) {
+                const int y = ty0 + ly * NPT + r;
+                const int yl = y < c.ny ? y : c.ny - 1;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    int xs, ys;
+                    pull_src(c, i, xl, yl, xs, ys);
+                    f[r][i] = fin[pidx(c, i, ys, xs)];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const int y = ty0 + ly * NPT + r;
+                if (x < c.nx && y < c.ny) collide_store_f64(a, c, x, y, f[r], list, nlist, fout);
+            }
+        } else {
+            float d[NPT][9];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const int y = ty0 + ly * NPT + r;
+                const int yl = y < c.ny ? y : c.ny - 1;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    int xs, ys;
+                    pull_src(c, i, xl, yl, xs, ys);
+                    d[r][i] = load_dev<ST>(fin, pidx(c, i, ys, xs), i, c);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const int y = ty0 + ly * NPT + r;
+                if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, x, y, d[r], list, nlist, fout);
             }
         }
     }
@@ -796,19 +852,27 @@ __global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
     // probe stencils (its own box grown by the probe reach), ascending.
     __shared__ int s_nb[kMaxNeighbours];
     __shared__ int s_nnb;
-    if (tid == 0) {
+    if (tid < 64) {
+        // lane j tests particle p_begin + j of each 64-particle chunk; the
+        // ballot keeps the list in ascending order
         int n = 0;
         const int grow = (int)ceil(dn) + 2;
-        for (int q = c.p_begin; q < c.p_end; ++q) {
-            const PartDev& Q = a.parts[q];
-            if (Q.bw <= 0) continue;
-            if (boxes_overlap(c, P->bx0 - grow, P->by0 - grow, P->bw + 2 * grow, P->bh + 2 * grow,
-                              Q.bx0, Q.by0, Q.bw, Q.bh)) {
-                if (n < kMaxNeighbours) s_nb[n] = q;
-                ++n;
+        for (int q0 = c.p_begin; q0 < c.p_end; q0 += 64) {
+            const int q = q0 + tid;
+            bool hit = false;
+            if (q < c.p_end) {
+                const PartDev& Q = a.parts[q];
+                hit = Q.bw > 0 && boxes_overlap(c, P->bx0 - grow, P->by0 - grow, P->bw + 2 * grow,
+                                                P->bh + 2 * grow, Q.bx0, Q.by0, Q.bw, Q.bh);
             }
+            const unsigned long long bal = __ballot(hit);
+            if (hit) {
+                const int pos = n + __popcll(bal & ((1ull << tid) - 1ull));
+                if (pos < kMaxNeighbours) s_nb[pos] = q;
+            }
+            n += __popcll(bal);
         }
-        s_nnb = n;
+        if (tid == 0) s_nnb = n;
     }
     __syncthreads();
     const int nnb = s_nnb;
