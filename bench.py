@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--autotune", action="store_true",
                     help="pick the lattice launch shape with the project autotuner first")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the batched / plain / FP16S comparison runs")
     return ap.parse_args()
 
 
@@ -80,6 +82,80 @@ def cpu_baseline(wl, seconds):
     return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{n} steps of channel 0 ({cfg['nx']}x{cfg['ny']}, {len(parts)} particle(s)) "
                       f"in FP64 on one host thread, {dt:.1f} s"}
+
+
+# Launch shapes picked by the autotuner for the comparison workloads.
+VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0),
+                  "large": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
+                  "large16": dict(tile_w=256, rows_per_thread=4, xcd_remap=0)}
+
+
+def kernel_source_sha():
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1606_01805_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(key):
+    """HBM bytes per lattice launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain
+    256 MiB copy), or None when the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(key)
+    if not e or e.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return e["bytes_per_launch"]
+
+
+def roofline(us_lattice, nodes, storage, traffic_key=None):
+    b = nodes * BYTES_PER_LUP[storage]
+    ach = b / (us_lattice * 1e-6) / 1e9
+    return {"kernel": "lattice_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(traffic_key) if traffic_key else None,
+            "bytes_per_launch": b, "us_per_launch": us_lattice}
+
+
+def run_variant(name, storage, steps, warm, plain=False, tuning=None):
+    """MLUPS of one comparison workload plus its lattice-kernel roofline."""
+    import torch
+
+    from paper_1606_01805_amd import Solver
+    from workloads import configs as C
+
+    wl = C.BY_NAME[name](storage=storage)
+    solvers = ([Solver([ch], tuning=tuning) for ch in wl.channels] if plain
+               else [Solver(wl.channels, tuning=tuning)])
+    for sv in solvers:
+        sv.step(warm, record=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sv in solvers:
+        sv.step(steps, record=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": wl.name, "storage": ["F64", "F32", "F16S"][storage],
+           "launch": "plain (one handle per channel)" if plain else "single handle, HIP graph",
+           "steps": steps, "MLUPS": wl.nodes * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3}
+    if not plain:
+        s0 = solvers[0]
+        s0.checkpoint_save(7)
+        us = s0.time_kernels(20)
+        s0.checkpoint_restore(7)
+        out["kernel_us"] = dict(zip(["ibm_force", "lattice", "traction"], [float(v) for v in us]))
+        key = {("ensemble", 1): "ensemble_f32", ("large", 1): "large_f32", ("large", 2): "large_f16s"}.get((name, storage))
+        out["roofline"] = roofline(float(us[1]), wl.nodes, storage, key)
+        out["tuning"] = s0.tuning()
+    for sv in solvers:
+        sv.close()
+    return out
 
 
 def main():
@@ -145,20 +221,13 @@ def main():
     names = ["ibm_force", "lattice", "traction"]
     k = int(max(range(3), key=lambda i: us[i]))
     nodes0 = sum(c["nx"] * c["ny"] for c in s0.cfgs)
-    lattice_bytes = nodes0 * BYTES_PER_LUP[storage]
-    if k == 1:
-        ach = lattice_bytes / (us[1] * 1e-6) / 1e9
-        roof = {"kernel": "lattice_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": lattice_bytes, "us_per_launch": us[1]}
-    else:
-        # the immersed-boundary kernels are latency bound: one workgroup per
-        # particle; report the lattice kernel's bandwidth beside them
-        ach = lattice_bytes / (us[1] * 1e-6) / 1e9
-        roof = {"kernel": "lattice_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": lattice_bytes, "us_per_launch": us[1],
-                "dominant_by_time": names[k]}
+    key = {("couette", 1): "couette_f32", ("ensemble", 1): "ensemble_f32", ("large", 1): "large_f32",
+           ("large", 2): "large_f16s"}.get((args.workload, storage))
+    roof = roofline(float(us[1]), nodes0, storage, key if not args.plain else None)
+    if k != 1:
+        # the particle kernels (one workgroup per particle) are latency bound;
+        # the lattice pass is the kernel that moves the step's bytes
+        roof["dominant_by_time"] = names[k]
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": warm, "ms_per_step": dt / steps * 1e3, "higher_is_better": True,
@@ -172,10 +241,18 @@ def main():
     }
     if tune_report:
         out["autotune_us_per_step"] = tune_report
+    for sv in solvers:
+        sv.close()
+    if not args.no_variants and args.workload == "couette":
+        # plain vs batched (256 uneven channels) and FP32 vs FP16S storage
+        out["variants"] = [
+            run_variant("ensemble", 1, 300, 30, tuning=VARIANT_TUNING["ensemble"]),
+            run_variant("ensemble", 1, 30, 5, plain=True),
+            run_variant("large", 1, 500, 50, tuning=VARIANT_TUNING["large"]),
+            run_variant("large", 2, 500, 50, tuning=VARIANT_TUNING["large16"]),
+        ]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    for s in solvers:
-        s.close()
     print(json.dumps(out), flush=True)
 
 

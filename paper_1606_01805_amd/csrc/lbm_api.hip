@@ -135,12 +135,7 @@ static int validate_cfg(const lbm_channel_config& c, int idx) {
 
 static size_t pitch_of(int nx) { return round_up((size_t)nx, 64); }
 
-static size_t plane_pad() {
-    const char* v = getenv("LBM_PLANE_PAD");
-    return v ? (size_t)atol(v) : 0;
-}
-
-static size_t plane_of(const lbm_channel_config& c) { return (size_t)c.ny * pitch_of(c.nx) + plane_pad(); }
+static size_t plane_of(const lbm_channel_config& c) { return (size_t)c.ny * pitch_of(c.nx); }
 
 static size_t buffer_bytes(const lbm_channel_config* cfg, int n, size_t elem) {
     size_t e = 0;
@@ -325,12 +320,6 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
     if (hipMemcpy(h->dflags, fl, sizeof(fl), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->dstep, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
         h->err = "upload of flags failed";
-        return fail_init(LBM_EDEVICE);
-    }
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
-        h->err = "creating the particle stream or its events failed";
         return fail_init(LBM_EDEVICE);
     }
     if ((r = build_tiles(h)) != LBM_OK) return fail_init(r);
@@ -678,6 +667,13 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
     if (t->use_graph != 0 && t->use_graph != 1) FAIL(h, LBM_EINVAL, "use_graph must be 0 or 1");
     if (t->xcd_remap != 0 && t->xcd_remap != 1) FAIL(h, LBM_EINVAL, "xcd_remap must be 0 or 1");
     if (t->overlap != 0 && t->overlap != 1) FAIL(h, LBM_EINVAL, "overlap must be 0 or 1");
+    if (t->overlap && !h->side) {
+        // the second stream exists only for handles that ask for the overlap
+        if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+            FAIL(h, LBM_EDEVICE, "creating the particle stream or its events failed");
+    }
     const bool tiles = t->tile_w != h->tune.tile_w || t->rows_per_thread != h->tune.rows_per_thread;
     h->tune = *t;
     if (tiles) h->tiles_dirty = true;
