@@ -480,14 +480,17 @@ int orc_get_marker_record(const orc_sim* s, int32_t p, double* out, int32_t cap)
 
 uint64_t orc_anchor_hash(const orc_sim* s) { return s->anchor_hash; }
 
-static void hash_anchor(orc_sim* s, double x, double y) {
+/* Running hash of every MLS stencil anchor used (markers and probes).  The
+ * anchors are piecewise constant in the particle state, so two runs with equal
+ * hashes differ only through the smooth part of the step map. */
+static void hash_anchor(uint64_t* hp, double x, double y) {
     int64_t a = (int64_t)floor(x + 0.5), b = (int64_t)floor(y + 0.5);
-    uint64_t h = s->anchor_hash;
+    uint64_t h = *hp;
     h ^= (uint64_t)a * 0x9E3779B97F4A7C15ULL;
     h *= 1099511628211ULL;
     h ^= (uint64_t)b * 0xC2B2AE3D27D4EB4FULL;
     h *= 1099511628211ULL;
-    s->anchor_hash = h;
+    *hp = h;
 }
 
 static int all_finite(const double* v, size_t n) {
@@ -505,7 +508,7 @@ static int all_finite(const double* v, size_t n) {
 static void surface_force(const orc_config* c, const double* rho, const double* ux,
                           const double* uy, double X, double Y, double th, double Om,
                           const double acc[3], int nm, const double* xi, const double* nu_b,
-                          const double* ds, double out[3]) {
+                          const double* ds, double out[3], uint64_t* hash) {
     const int nx = c->nx;
     const double nu = (c->tau - 0.5) / 3.0;
     double cs = cos(th), sn = sin(th);
@@ -520,6 +523,7 @@ static void surface_force(const orc_config* c, const double* rho, const double* 
         int32_t ni[9], nj[9], ok[9];
         double phi[9], dpx[9], dpy[9];
         orc_mls(c, xp, yp, ni, nj, ok, phi, dpx, dpy);
+        if (hash) hash_anchor(hash, xp, yp);
         double rP = 0.0, dudx = 0.0, dudy = 0.0, dvdx = 0.0, dvdy = 0.0;
         for (int k = 0; k < 9; ++k) {
             if (!ok[k]) continue;
@@ -552,7 +556,7 @@ void orc_surface_force(const orc_config* cfg, const double* rho, const double* u
                        const double* uy, const orc_particle_desc* d, const double acc[3],
                        double out[3]) {
     surface_force(cfg, rho, ux, uy, d->x, d->y, d->theta, d->omega, acc, d->n_markers, d->xi,
-                  d->nrm, d->ds, out);
+                  d->nrm, d->ds, out, NULL);
 }
 
 /* One time step; returns 1 if the state became invalid. */
@@ -598,7 +602,7 @@ static int one_step(orc_sim* s, double* rec_out) {
             int32_t ni[9], nj[9], ok[9];
             double phi[9], dpx[9], dpy[9];
             orc_mls(c, xl, yl, ni, nj, ok, phi, dpx, dpy);
-            hash_anchor(s, xl, yl);
+            hash_anchor(&s->anchor_hash, xl, yl);
             double Ux = 0.0, Uy = 0.0;
             for (int k = 0; k < 9; ++k) {
                 if (!ok[k]) continue;
@@ -647,7 +651,7 @@ static int one_step(orc_sim* s, double* rec_out) {
         double out[3];
         double acc[3] = {p->acc[0], p->acc[1], p->alp};
         surface_force(c, s->rho, s->ux, s->uy, p->X[0], p->X[1], p->th, p->Om, acc, p->nm,
-                      p->xi, p->nu, p->ds, out);
+                      p->xi, p->nu, p->ds, out, &s->anchor_hash);
         double Fx = out[0], Fy = out[1], Mz = out[2];
         p->F[0] = Fx;
         p->F[1] = Fy;
