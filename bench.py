@@ -158,6 +158,51 @@ def run_variant(name, storage, steps, warm, plain=False, tuning=None):
     return out
 
 
+def adjoint_leg(storage=1, steps=2000, seg=100):
+    """Cost of one reverse-mode gradient on the 256x64 Couette case: the
+    checkpointed forward (graph replay, a checkpoint every `seg` steps) and
+    the adjoint sweep (every segment recomputed into the tape and reversed),
+    per step, and their ratio."""
+    import torch
+
+    from paper_1606_01805_amd import Solver
+    from workloads import configs as C
+
+    wl = C.adjoint_case(storage=storage)
+    s = Solver(wl.channels)
+    nseg = steps // seg
+    s.checkpoint_save(nseg + 1)
+    s.step(200, record=False)  # warm-up (graphs built)
+    s.checkpoint_restore(nseg + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, record=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    s.checkpoint_restore(nseg + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nseg):
+        s.checkpoint_save(k)
+        s.step(seg, record=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    seed = [[0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0]]
+    t0 = time.perf_counter()
+    s.adjoint_begin(seed, seg)
+    for k in reversed(range(nseg)):
+        s.adjoint_segment(k, seg)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    s.close()
+    return {"workload": wl.name, "storage": ["F64", "F32", "F16S"][storage], "steps": steps, "segment": seg,
+            "forward_us_per_step": t_plain / steps * 1e6,
+            "forward_checkpointed_us_per_step": t_fwd / steps * 1e6,
+            "adjoint_us_per_step": t_adj / steps * 1e6,
+            "adjoint_over_forward": t_adj / t_plain,
+            "note": "adjoint time includes recomputing each segment from its checkpoint"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -251,6 +296,9 @@ def main():
             run_variant("large", 1, 500, 50, tuning=VARIANT_TUNING["large"]),
             run_variant("large", 2, 500, 50, tuning=VARIANT_TUNING["large16"]),
         ]
+        out["adjoint"] = adjoint_leg()
+    if args.workload == "adjoint":
+        out["adjoint"] = adjoint_leg(storage=storage)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

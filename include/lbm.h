@@ -67,6 +67,11 @@ enum { LBM_W_EXP = 0, LBM_W_CUBIC = 1, LBM_W_QUARTIC = 2, LBM_W_COSINE = 3 };
 enum { LBM_SPREAD_SEGMENT = 0, LBM_SPREAD_UNIT = 1 };
 
 #define LBM_PSTATE 10 /* per particle: x, y, theta, u, v, omega, Fx, Fy, M, channel */
+/* per particle, lbm_adjoint_gradients: dJ/d of the state at the adjoint
+ * position, X(2), X_prev(2), theta, theta_prev, V(2), V_prev(2), omega,
+ * omega_prev, acc(2), alpha (the lagged accelerations of Sec. 1.3), then
+ * dJ/dm and dJ/dI accumulated over the reversed steps */
+#define LBM_AGRAD 17
 
 /* One channel (an independent lattice).  Channels of one handle must share
  * `storage`.  At most one axis may carry Zou-He walls (no corners). */
@@ -179,7 +184,7 @@ int lbm_get_populations(lbm_handle* h, int32_t channel, double* f);
 int lbm_set_populations(lbm_handle* h, int32_t channel, const double* f);
 
 /* Save / restore the complete state (populations, particles, step counter) in
- * slot 0..7; slots are allocated on first use.  Restoring a slot saved with a
+ * slot 0..63; slots are allocated on first use.  Restoring a slot saved with a
  * different particle set is LBM_ESTATE. */
 int lbm_checkpoint_save(lbm_handle* h, int32_t slot);
 int lbm_checkpoint_restore(lbm_handle* h, int32_t slot);
@@ -195,6 +200,56 @@ int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
  * launches run real steps, so the state advances by reps steps per kernel
  * phase; use a checkpoint around the call to keep it. */
 int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]);
+
+/* ---- Discrete adjoint of the step (reverse-mode gradients) ----------------
+ * J is a linear function of the particle records after the last step taken:
+ * J = sum_p seed[p] . record[p] (LBM_PSTATE entries; the channel entry is
+ * ignored).  Its gradient is computed by reversing the steps segment by
+ * segment: each segment restarts from a checkpoint (lbm_checkpoint_save),
+ * recomputes its steps into a tape and reverses them with the transposes of
+ * the moments and Guo collision (Eqs. (4)-(7)), the IB interpolation, force
+ * and spreading (Eqs. (8)-(12)) including the motion of the MLS weights with
+ * the markers, the surface stress, force and moment (Eqs. (13), (14)), BDF2
+ * (Eqs. (15), (16)), streaming and the Zou-He closure (App. A).  MLS stencil
+ * anchors are held fixed (the step map is piecewise smooth in the particle
+ * state).  Sums have a fixed order: results are bitwise reproducible.
+ *
+ * lbm_adjoint_begin: start at the current step with the seed
+ * [n_particles][LBM_PSTATE] (host, particles in the order they were added)
+ * and allocate a tape of max_segment steps: max_segment population buffers
+ * plus force patches and particle snapshots.  Errors: LBM_EINVAL (NULL or
+ * non-finite seed, probe reach wider than the channel), LBM_ENOMEM. */
+int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_segment);
+
+/* Reverse n_steps (1..max_segment) steps that end at the current adjoint
+ * position and start at the checkpoint in `slot`: restores it, recomputes the
+ * steps, reverses them, and restores the checkpoint again (the forward state
+ * is left at the checkpoint).  The adjoint position moves back by n_steps.
+ * Segments must be taken from the last one backwards.  Errors: LBM_ESTATE (no
+ * adjoint begun, empty slot, or checkpoint step + n_steps != position),
+ * LBM_EINVAL, LBM_EUNSTABLE / LBM_ECAPACITY from the recomputation (the
+ * adjoint is then abandoned). */
+int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n_steps);
+
+/* Gradients at the current adjoint position (host outputs, each may be NULL):
+ *   part_out   [n_particles][LBM_AGRAD], particles in the order added; at
+ *              position 0 the derivative with respect to an initial value
+ *              is the sum of its current and previous slots (the BDF2
+ *              history starts equal to the initial state);
+ *   marker_out [sum of n_markers][5]: dJ/d xi (2), d nrm (2), d ds per
+ *              marker, particles in the order added;
+ *   wall_out   [n_channels][4][2]: dJ/d u_wall.  At position 0 this includes
+ *              the Couette start (Sec. 3.1) unless the populations were
+ *              replaced with lbm_set_populations. */
+int lbm_adjoint_gradients(lbm_handle* h, double* part_out, double* marker_out, double* wall_out);
+
+/* dJ/d populations at the adjoint position, [9][ny][nx] FP64 (host).  On wall
+ * nodes the entries are with respect to the streamed populations before the
+ * Zou-He closure (zero for the three it reconstructs). */
+int lbm_adjoint_field(lbm_handle* h, int32_t channel, double* out);
+
+/* Step index the adjoint currently refers to (-1: none in progress). */
+int64_t lbm_adjoint_position(const lbm_handle* h);
 
 /* Total steps taken by the handle. */
 int64_t lbm_steps_done(const lbm_handle* h);

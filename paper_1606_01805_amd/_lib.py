@@ -16,6 +16,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ECAPACITY, LBM_EUNS
 STATUS_NAMES = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EDEVICE", 4: "LBM_ESTATE",
                 5: "LBM_ECAPACITY", 6: "LBM_EUNSTABLE"}
 PSTATE = 10
+AGRAD = 17
 STORE_F64, STORE_F32, STORE_F16S = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +67,11 @@ SIGNATURES = {
     "lbm_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "lbm_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
     "lbm_time_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
+    "lbm_adjoint_begin": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int32]),
+    "lbm_adjoint_segment": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_adjoint_gradients": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
+    "lbm_adjoint_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
+    "lbm_adjoint_position": (ctypes.c_int64, [ctypes.c_void_p]),
     "lbm_steps_done": (ctypes.c_int64, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "lbm_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpaper_lbm.so")
-SOURCES = ["csrc/lbm_kernels.hip", "csrc/lbm_api.hip"]
+SOURCES = ["csrc/lbm_kernels.hip", "csrc/lbm_adjoint.hip", "csrc/lbm_api.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: no FMA contraction, so the FP64 form performs exactly

@@ -28,6 +28,8 @@ struct PartHost {
     int cap;
 };
 
+constexpr int kCheckpoints = 64;
+
 struct Checkpoint {
     void* f = nullptr;
     PartDev* p = nullptr;
@@ -77,7 +79,29 @@ struct lbm_handle {
     long long steps = 0;
     bool finalized = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    Checkpoint ck[8];
+    Checkpoint ck[kCheckpoints];
+    long long cells = 0;           // force-patch pool size
+    bool pop_modified = false;     // populations replaced since lbm_init
+    // adjoint (lbm_adjoint_*)
+    int adj_seg = 0;               // tape capacity in steps
+    std::vector<void*> tape_f;     // post-collision populations of each taped step
+    PartDev* tape_p = nullptr;     // [adj_seg + 1][nparts] particle snapshots
+    double2* tape_patch = nullptr; // [adj_seg][cells] force patches
+    void* lam[2] = {nullptr, nullptr};
+    size_t lam_bytes = 0;
+    int lcur = 0;
+    int apar = 0;
+    AdjPart* dap = nullptr;
+    double* dapatch = nullptr;
+    double* dgmk = nullptr;
+    double* dpscr = nullptr;
+    double* dgwall = nullptr;
+    long long* dgwoff = nullptr;
+    int* datlist = nullptr;
+    double* dgout = nullptr;
+    size_t gwall_n = 0;
+    long long adj_pos = -1;        // step of the state the adjoint currently refers to
+    bool adj_first = false;
     std::string err;
 };
 
@@ -431,6 +455,7 @@ static int finalize(lbm_handle* h) {
         ch.p_end = k + 1;
     }
     h->nparts = np;
+    h->cells = cells;
     const size_t nmk = std::max<size_t>(ds.size(), 1);
     HIPCHK(h, hipMalloc(&h->dparts, sizeof(PartDev) * std::max(np, 1)));
     HIPCHK(h, hipMalloc(&h->dxi, sizeof(double2) * nmk));
@@ -507,6 +532,7 @@ static int check_flags(lbm_handle* h) {
     int fl[4];
     HIPCHK(h, hipMemcpyAsync(fl, h->dflags, sizeof(fl), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (fl[2] & 2) FAIL(h, LBM_ECAPACITY, "a particle's probe reach outgrew its adjoint patch");
     if (fl[2]) FAIL(h, LBM_ECAPACITY, "a particle outgrew its force patch");
     if (fl[0])
         FAIL(h, LBM_EUNSTABLE, "non-finite or non-positive density or particle state in step %d (counting from 1)",
@@ -612,6 +638,7 @@ extern "C" int lbm_set_populations(lbm_handle* h, int32_t ch, const double* f) {
     if (ch < 0 || ch >= (int)h->cfg.size() || !f) FAIL(h, LBM_EINVAL, "bad channel or NULL input");
     const size_t n = (size_t)h->cfg[ch].nx * h->cfg[ch].ny;
     if (!finite_all(f, 9 * n)) FAIL(h, LBM_EINVAL, "non-finite population");
+    h->pop_modified = true;
     double* d = nullptr;
     HIPCHK(h, hipMalloc(&d, sizeof(double) * 9 * n));
     hipError_t e = hipMemcpyAsync(d, f, sizeof(double) * 9 * n, hipMemcpyHostToDevice, h->stream);
@@ -625,7 +652,7 @@ extern "C" int lbm_set_populations(lbm_handle* h, int32_t ch, const double* f) {
 
 extern "C" int lbm_checkpoint_save(lbm_handle* h, int32_t slot) {
     if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
-    if (slot < 0 || slot >= 8) FAIL(h, LBM_EINVAL, "slot must be in 0..7");
+    if (slot < 0 || slot >= kCheckpoints) FAIL(h, LBM_EINVAL, "slot must be in 0..%d", kCheckpoints - 1);
     int r;
     if ((r = finalize(h)) != LBM_OK) return r;
     Checkpoint& c = h->ck[slot];
@@ -644,7 +671,7 @@ extern "C" int lbm_checkpoint_save(lbm_handle* h, int32_t slot) {
 
 extern "C" int lbm_checkpoint_restore(lbm_handle* h, int32_t slot) {
     if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
-    if (slot < 0 || slot >= 8) FAIL(h, LBM_EINVAL, "slot must be in 0..7");
+    if (slot < 0 || slot >= kCheckpoints) FAIL(h, LBM_EINVAL, "slot must be in 0..%d", kCheckpoints - 1);
     Checkpoint& c = h->ck[slot];
     if (!c.f || c.nparts != h->nparts || !h->finalized) FAIL(h, LBM_ESTATE, "slot %d holds no compatible checkpoint", slot);
     HIPCHK(h, hipMemcpyAsync(h->buf[c.cur], c.f, h->buf_bytes, hipMemcpyDeviceToDevice, h->stream));
@@ -721,6 +748,253 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
     return check_flags(h);
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+// ---------------------------------------------------------------------------
+static void free_adjoint(lbm_handle* h) {
+    for (void* p : h->tape_f)
+        if (p) (void)hipFree(p);
+    h->tape_f.clear();
+    void* ptrs[] = {h->tape_p, h->tape_patch, h->lam[0], h->dap, h->dapatch, h->dgmk, h->dpscr,
+                    h->dgwall, h->dgwoff, h->datlist, h->dgout};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    h->tape_p = nullptr;
+    h->tape_patch = nullptr;
+    h->lam[0] = h->lam[1] = nullptr;
+    h->dap = nullptr;
+    h->dapatch = nullptr;
+    h->dgmk = h->dpscr = h->dgwall = h->dgout = nullptr;
+    h->dgwoff = nullptr;
+    h->datlist = nullptr;
+    h->adj_seg = 0;
+    h->adj_pos = -1;
+}
+
+static AdjArgs adj_args(lbm_handle* h) {
+    AdjArgs a{};
+    a.s = make_args(h, h->cur);
+    a.s.parity = h->apar;
+    a.ap = h->dap;
+    a.apatch = h->dapatch;
+    a.gmk = h->dgmk;
+    a.pscr = h->dpscr;
+    a.gwall = h->dgwall;
+    a.gw_off = h->dgwoff;
+    a.atlist = h->datlist;
+    a.lam_in = h->lam[h->lcur];
+    a.lam_out = h->lam[1 - h->lcur];
+    return a;
+}
+
+extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_segment) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (max_segment < 1) FAIL(h, LBM_EINVAL, "max_segment must be >= 1");
+    int r;
+    if ((r = finalize(h)) != LBM_OK) return r;
+    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
+    const int np = h->nparts;
+    if (np > 0 && !seed) FAIL(h, LBM_EINVAL, "seed is NULL");
+    if (np > 0 && !finite_all(seed, 10 * (size_t)np)) FAIL(h, LBM_EINVAL, "non-finite seed");
+    const int nch = (int)h->cfg.size();
+    // adjoint patches: the stencils of the markers and of their probes
+    std::vector<AdjPart> ap(std::max(np, 1));
+    long long acells = 0;
+    for (int k = 0; k < np; ++k) {
+        const PartHost& P = h->parts[h->user_of_dev[k]];
+        const lbm_channel_config& c = h->cfg[P.chan];
+        const int side = (int)std::ceil(2.0 * (P.rb + c.probe_dn)) + 6;
+        if (side > c.nx || side > c.ny)
+            FAIL(h, LBM_EINVAL, "particle %d: probe reach wider than its channel", h->user_of_dev[k]);
+        AdjPart& A = ap[k];
+        memset(&A, 0, sizeof(A));
+        const double* sd = seed + 10 * h->user_of_dev[k];
+        A.l[AL_X] = sd[0];
+        A.l[AL_X + 1] = sd[1];
+        A.l[AL_TH] = sd[2];
+        A.l[AL_V] = sd[3];
+        A.l[AL_V + 1] = sd[4];
+        A.l[AL_OM] = sd[5];
+        A.seed[0] = sd[6];
+        A.seed[1] = sd[7];
+        A.seed[2] = sd[8];
+        A.acap = side * side;
+        A.aoff = acells;
+        acells += A.acap;
+    }
+    std::vector<long long> gwoff(nch);
+    size_t gw = 0;
+    for (int c = 0; c < nch; ++c) {
+        const lbm_channel_config& cf = h->cfg[c];
+        gwoff[c] = (long long)gw;
+        const size_t nwall = cf.bc_y == LBM_BC_ZOUHE ? 2 * (size_t)cf.nx : (cf.bc_x == LBM_BC_ZOUHE ? 2 * (size_t)cf.ny : 0);
+        gw += 2 * nwall + (size_t)cf.ny;
+    }
+    free_adjoint(h);
+    size_t planes = 0;
+    for (auto& c : h->cfg) planes += 9 * plane_of(c);
+    h->lam_bytes = round_up(planes * (h->store == LBM_STORE_F64 ? 8 : 4), 4096);
+    const size_t nmk = std::max<size_t>(1, [&] {
+        size_t m = 0;
+        for (auto& p : h->parts) m += p.d.n_markers;
+        return m;
+    }());
+    const size_t nt = h->htiles.size();
+    h->tape_f.assign(max_segment, nullptr);
+    for (int t = 0; t < max_segment; ++t)
+        if (hipMalloc(&h->tape_f[t], h->buf_bytes) != hipSuccess) {
+            free_adjoint(h);
+            FAIL(h, LBM_ENOMEM, "tape of %d steps (%zu bytes each) does not fit", max_segment, h->buf_bytes);
+        }
+    auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+    bool ok = alloc((void**)&h->tape_p, sizeof(PartDev) * (size_t)(max_segment + 1) * std::max(np, 1)) &&
+              alloc((void**)&h->tape_patch, sizeof(double2) * (size_t)max_segment * std::max<long long>(h->cells, 1)) &&
+              alloc(&h->lam[0], 2 * h->lam_bytes) && alloc((void**)&h->dap, sizeof(AdjPart) * ap.size()) &&
+              alloc((void**)&h->dapatch, sizeof(double) * kAdjCell * std::max<long long>(acells, 1)) &&
+              alloc((void**)&h->dgmk, sizeof(double) * 5 * nmk) && alloc((void**)&h->dpscr, sizeof(double) * 8 * nmk) &&
+              alloc((void**)&h->dgwall, sizeof(double) * std::max<size_t>(gw, 1)) &&
+              alloc((void**)&h->dgwoff, sizeof(long long) * nch) &&
+              alloc((void**)&h->datlist, sizeof(int) * 2 * nt * kTileList) && alloc((void**)&h->dgout, sizeof(double) * 8 * nch);
+    if (!ok) {
+        free_adjoint(h);
+        FAIL(h, LBM_ENOMEM, "allocation of the adjoint state failed");
+    }
+    h->lam[1] = (char*)h->lam[0] + h->lam_bytes;
+    h->adj_seg = max_segment;
+    h->gwall_n = gw;
+    HIPCHK(h, hipMemsetAsync(h->lam[0], 0, 2 * h->lam_bytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->dgmk, 0, sizeof(double) * 5 * nmk, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->dgwall, 0, sizeof(double) * std::max<size_t>(gw, 1), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->datlist, 0, sizeof(int) * 2 * nt * kTileList, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->dap, ap.data(), sizeof(AdjPart) * ap.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->dgwoff, gwoff.data(), sizeof(long long) * nch, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->lcur = 0;
+    h->apar = 0;
+    h->adj_pos = h->steps;
+    h->adj_first = true;
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (h->adj_pos < 0) FAIL(h, LBM_ESTATE, "no adjoint in progress (call lbm_adjoint_begin)");
+    if (slot < 0 || slot >= kCheckpoints) FAIL(h, LBM_EINVAL, "slot must be in 0..%d", kCheckpoints - 1);
+    if (n < 1 || n > h->adj_seg) FAIL(h, LBM_EINVAL, "segment length must be in 1..%d", h->adj_seg);
+    const Checkpoint& ck = h->ck[slot];
+    if (!ck.f || ck.nparts != h->nparts) FAIL(h, LBM_ESTATE, "slot %d holds no compatible checkpoint", slot);
+    if (ck.steps + n != h->adj_pos)
+        FAIL(h, LBM_ESTATE, "checkpoint at step %lld plus %d steps does not reach the adjoint position %lld",
+             ck.steps, n, h->adj_pos);
+    int r;
+    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
+    if ((r = lbm_checkpoint_restore(h, slot)) != LBM_OK) return r;
+    const int np = h->nparts;
+    // recompute the segment into the tape
+    for (int t = 0; t < n; ++t) {
+        StepArgs a = make_args(h, h->cur, (h->cur + t) & 1);
+        a.fin = t == 0 ? h->buf[h->cur] : h->tape_f[t - 1];
+        a.fout = h->tape_f[t];
+        a.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
+        HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+        if (np)
+            HIPCHK(h, hipMemcpyAsync(h->tape_p + (size_t)t * np, h->dparts, sizeof(PartDev) * np,
+                                     hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+        HIPCHK(h, launch_traction(h->store, a, h->stream));
+    }
+    if (np)
+        HIPCHK(h, hipMemcpyAsync(h->tape_p + (size_t)n * np, h->dparts, sizeof(PartDev) * np,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    if ((r = check_flags(h)) != LBM_OK) return r;
+    // reverse sweep
+    for (int t = n - 1; t >= 0; --t) {
+        AdjArgs a = adj_args(h);
+        a.s.fin = t == 0 ? h->buf[h->cur] : h->tape_f[t - 1];
+        a.s.parts = h->tape_p + (size_t)t * np;
+        a.s.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
+        a.pnext = h->tape_p + (size_t)(t + 1) * np;
+        a.first = h->adj_first ? 1 : 0;
+        HIPCHK(h, launch_adj_traction(h->store, a, h->stream));
+        HIPCHK(h, launch_adj_ibm(h->store, a, h->stream));
+        HIPCHK(h, launch_adj_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+        h->lcur = 1 - h->lcur;
+        h->apar = 1 - h->apar;
+        h->adj_first = false;
+    }
+    const int rf = check_flags(h);
+    // leave the forward state at the segment's checkpoint
+    if ((r = lbm_checkpoint_restore(h, slot)) != LBM_OK) return r;
+    if (rf != LBM_OK) {
+        h->adj_pos = -1;  // the adjoint is incomplete: a new lbm_adjoint_begin is needed
+        return rf;
+    }
+    h->adj_pos -= n;
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_gradients(lbm_handle* h, double* part_out, double* marker_out, double* wall_out) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (h->adj_pos < 0) FAIL(h, LBM_ESTATE, "no adjoint in progress (call lbm_adjoint_begin)");
+    const int np = h->nparts, nch = (int)h->cfg.size();
+    AdjArgs a = adj_args(h);
+    a.lam_in = h->lam[h->lcur];
+    for (int c = 0; c < nch; ++c) {
+        const int with_init = h->adj_pos == 0 && !h->pop_modified && h->cfg[c].init == LBM_INIT_COUETTE;
+        HIPCHK(h, launch_adj_finish(h->store, a, c, with_init, h->dgout + 8 * c, h->stream));
+    }
+    std::vector<AdjPart> ap(std::max(np, 1));
+    size_t nmk = 0;
+    for (auto& p : h->parts) nmk += p.d.n_markers;
+    std::vector<double> gmk(5 * std::max<size_t>(nmk, 1)), gout(8 * nch);
+    if (np) HIPCHK(h, hipMemcpyAsync(ap.data(), h->dap, sizeof(AdjPart) * np, hipMemcpyDeviceToHost, h->stream));
+    if (nmk) HIPCHK(h, hipMemcpyAsync(gmk.data(), h->dgmk, sizeof(double) * 5 * nmk, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(gout.data(), h->dgout, sizeof(double) * 8 * nch, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (part_out)
+        for (int u = 0; u < np; ++u) {
+            const AdjPart& A = ap[h->dev_of_user[u]];
+            double* o = part_out + (size_t)u * LBM_AGRAD;
+            for (int j = 0; j < AL_N; ++j) o[j] = A.l[j];
+            o[AL_N] = A.gm;
+            o[AL_N + 1] = A.gI;
+        }
+    if (marker_out) {
+        // device marker order follows the device particle order
+        std::vector<size_t> dbeg(np + 1, 0);
+        for (int k = 0; k < np; ++k) dbeg[k + 1] = dbeg[k] + h->parts[h->user_of_dev[k]].d.n_markers;
+        size_t o = 0;
+        for (int u = 0; u < np; ++u) {
+            const int k = h->dev_of_user[u];
+            const size_t m = h->parts[u].d.n_markers;
+            memcpy(marker_out + 5 * o, gmk.data() + 5 * dbeg[k], sizeof(double) * 5 * m);
+            o += m;
+        }
+    }
+    if (wall_out) memcpy(wall_out, gout.data(), sizeof(double) * 8 * nch);
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_field(lbm_handle* h, int32_t ch, double* out) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (h->adj_pos < 0) FAIL(h, LBM_ESTATE, "no adjoint in progress (call lbm_adjoint_begin)");
+    if (ch < 0 || ch >= (int)h->cfg.size() || !out) FAIL(h, LBM_EINVAL, "bad channel or NULL output");
+    const size_t n = (size_t)h->cfg[ch].nx * h->cfg[ch].ny;
+    double* d = nullptr;
+    HIPCHK(h, hipMalloc(&d, sizeof(double) * 9 * n));
+    AdjArgs a = adj_args(h);
+    a.lam_in = h->lam[h->lcur];
+    hipError_t e = launch_adj_field(h->store, a, ch, d, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, sizeof(double) * 9 * n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    HIPCHK(h, e);
+    return LBM_OK;
+}
+
+extern "C" int64_t lbm_adjoint_position(const lbm_handle* h) { return h ? h->adj_pos : -1; }
+
 extern "C" int64_t lbm_steps_done(const lbm_handle* h) { return h ? h->steps : -1; }
 
 extern "C" const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
@@ -728,6 +1002,7 @@ extern "C" const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c
 extern "C" int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;
     drop_graphs(h);
+    free_adjoint(h);
     if (h->side) (void)hipStreamSynchronize(h->side);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);

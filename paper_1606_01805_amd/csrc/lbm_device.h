@@ -1,0 +1,493 @@
+// Device helpers shared by the forward and adjoint kernels of the coupled
+// LBM / MLS-IBM step: lattice constants, population addressing and pulls,
+// Zou-He closures, moments, force-patch lookups, the MLS operator and the
+// per-tile particle lists.
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "lbm_internal.h"
+
+namespace lbmk {
+
+// D2Q9 velocities in the order of Eq. (3) and their weights.
+__device__ __forceinline__ constexpr int ex(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr int ey(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr double wd(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+__device__ __forceinline__ constexpr float wf(int i) {
+    return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+}
+__device__ __forceinline__ constexpr int wclass(int i) { return i == 0 ? 0 : (i < 5 ? 1 : 2); }
+
+template <int ST> struct Sto;
+template <> struct Sto<ST_F64> { using T = double; };
+template <> struct Sto<ST_F32> { using T = float; };
+template <> struct Sto<ST_F16S> { using T = __half; };
+
+__device__ __forceinline__ long long pidx(const ChanDev& c, int i, int y, int x) {
+    return c.off + (long long)i * c.plane + (long long)y * c.pitch + x;
+}
+
+// Source node of population i for a pull at (x, y).  Periodic axes wrap.  A
+// source beyond a wall-bounded edge is replaced by the node itself (always a
+// valid address): that population enters through the wall and is
+// overwritten by the wall closure, which reads only the known populations.
+__device__ __forceinline__ int pull_coord(int v, int self, int n, bool periodic) {
+    const int lo = v < 0, hi = v >= n;
+    return periodic ? v + (lo - hi) * n : ((lo | hi) ? self : v);
+}
+
+__device__ __forceinline__ void pull_src(const ChanDev& c, int i, int x, int y, int& xs, int& ys) {
+    xs = pull_coord(x - ex(i), x, c.nx, c.bcx == 0);
+    ys = pull_coord(y - ey(i), y, c.ny, c.bcy == 0);
+}
+
+// Wave-uniform copies (scalar registers) of values every lane holds alike.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ long long uni(long long v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double(uni(__double_as_longlong(v))); }
+
+// The channel descriptor a whole workgroup works on, in scalar registers:
+// branches on the boundary kinds stay uniform.
+__device__ __forceinline__ ChanDev load_chan(const ChanDev* p) {
+    ChanDev c;
+    c.nx = uni(p->nx);
+    c.ny = uni(p->ny);
+    c.pitch = uni(p->pitch);
+    c.bcx = uni(p->bcx);
+    c.bcy = uni(p->bcy);
+    c.p_begin = uni(p->p_begin);
+    c.p_end = uni(p->p_end);
+    c.kernel = uni(p->kernel);
+    c.spread_unit = uni(p->spread_unit);
+    c.pad0 = 0;
+    c.off = uni(p->off);
+    c.plane = uni(p->plane);
+    c.tau = uni(p->tau);
+    c.nu = uni(p->nu);
+    for (int s = 0; s < 4; ++s)
+        for (int k = 0; k < 2; ++k) {
+            c.uw[s][k] = uni(p->uw[s][k]);
+            c.f_uw[s][k] = uni(p->f_uw[s][k]);
+        }
+    for (int k = 0; k < 2; ++k) {
+        c.g[k] = uni(p->g[k]);
+        c.grav[k] = uni(p->grav[k]);
+        c.f_g[k] = uni(p->f_g[k]);
+    }
+    c.rw = uni(p->rw);
+    c.alpha = uni(p->alpha);
+    c.dn = uni(p->dn);
+    c.f_omega = uni(p->f_omega);
+    c.f_pref = uni(p->f_pref);
+    for (int k = 0; k < 3; ++k) {
+        c.sc[k] = uni(p->sc[k]);
+        c.isc[k] = uni(p->isc[k]);
+    }
+    c.tile0 = uni(p->tile0);
+    c.tiles_x = uni(p->tiles_x);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 form: populations f_i, expressions in reference order.
+// ---------------------------------------------------------------------------
+// Zou-He known-velocity wall (Sec. 1.1): mass and normal momentum fix rho,
+// bounce-back of the non-equilibrium normal population, tangential momentum
+// for the two diagonals; target momentum m = rho u_w - g/2.
+__device__ __forceinline__ void zouhe_f64(int side, double f[9], double uwx, double uwy,
+                                          double gx, double gy) {
+    double rho, mx, my;
+    if (side == 2) {
+        rho = (f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]) - 0.5 * gy) / (1.0 - uwy);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[2] = f[4] + 2.0 * my / 3.0;
+        f[5] = f[7] - 0.5 * (f[1] - f[3]) + 0.5 * mx + my / 6.0;
+        f[6] = f[8] + 0.5 * (f[1] - f[3]) - 0.5 * mx + my / 6.0;
+    } else if (side == 3) {
+        rho = (f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]) + 0.5 * gy) / (1.0 + uwy);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[4] = f[2] - 2.0 * my / 3.0;
+        f[7] = f[5] + 0.5 * (f[1] - f[3]) - 0.5 * mx - my / 6.0;
+        f[8] = f[6] - 0.5 * (f[1] - f[3]) + 0.5 * mx - my / 6.0;
+    } else if (side == 0) {
+        rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7]) - 0.5 * gx) / (1.0 - uwx);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[1] = f[3] + 2.0 * mx / 3.0;
+        f[5] = f[7] - 0.5 * (f[2] - f[4]) + mx / 6.0 + 0.5 * my;
+        f[8] = f[6] + 0.5 * (f[2] - f[4]) + mx / 6.0 - 0.5 * my;
+    } else {
+        rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8]) + 0.5 * gx) / (1.0 + uwx);
+        mx = rho * uwx - 0.5 * gx;
+        my = rho * uwy - 0.5 * gy;
+        f[3] = f[1] - 2.0 * mx / 3.0;
+        f[7] = f[5] + 0.5 * (f[2] - f[4]) - mx / 6.0 - 0.5 * my;
+        f[6] = f[8] - 0.5 * (f[2] - f[4]) - mx / 6.0 + 0.5 * my;
+    }
+}
+
+__device__ __forceinline__ void walls_f64(const ChanDev& c, int x, int y, double f[9]) {
+    if (c.bcy == 1) {
+        if (y == 0) zouhe_f64(2, f, c.uw[2][0], c.uw[2][1], c.g[0], c.g[1]);
+        else if (y == c.ny - 1) zouhe_f64(3, f, c.uw[3][0], c.uw[3][1], c.g[0], c.g[1]);
+    }
+    if (c.bcx == 1) {
+        if (x == 0) zouhe_f64(0, f, c.uw[0][0], c.uw[0][1], c.g[0], c.g[1]);
+        else if (x == c.nx - 1) zouhe_f64(1, f, c.uw[1][0], c.uw[1][1], c.g[0], c.g[1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduced forms: deviations d_i = f_i - w_i in FP32.
+// ---------------------------------------------------------------------------
+template <int ST>
+__device__ __forceinline__ float load_dev(const typename Sto<ST>::T* p, long long k, int i,
+                                          const ChanDev& c) {
+    if constexpr (ST == ST_F32) {
+        return p[k];
+    } else {
+        return __half2float(p[k]) * c.isc[wclass(i)];
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void store_dev(typename Sto<ST>::T* p, long long k, int i, float d,
+                                          const ChanDev& c) {
+    if constexpr (ST == ST_F32) {
+        p[k] = d;
+    } else {
+        p[k] = __float2half_rn(d * c.sc[wclass(i)]);
+    }
+}
+
+// The Zou-He closure of zouhe_f64 written for deviations: the weights of the
+// known populations entering rho sum to 1, and w_i cancels in every
+// difference.
+__device__ __forceinline__ void zouhe_dev(int side, float d[9], float uwx, float uwy, float gx,
+                                          float gy) {
+    float drho, rho, mx, my;
+    if (side == 2) {
+        float s = d[0] + d[1] + d[3] + 2.0f * (d[4] + d[7] + d[8]);
+        drho = (s - 0.5f * gy + uwy) / (1.0f - uwy);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[2] = d[4] + (2.0f / 3.0f) * my;
+        d[5] = d[7] - 0.5f * (d[1] - d[3]) + 0.5f * mx + my * (1.0f / 6.0f);
+        d[6] = d[8] + 0.5f * (d[1] - d[3]) - 0.5f * mx + my * (1.0f / 6.0f);
+    } else if (side == 3) {
+        float s = d[0] + d[1] + d[3] + 2.0f * (d[2] + d[5] + d[6]);
+        drho = (s + 0.5f * gy - uwy) / (1.0f + uwy);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[4] = d[2] - (2.0f / 3.0f) * my;
+        d[7] = d[5] + 0.5f * (d[1] - d[3]) - 0.5f * mx - my * (1.0f / 6.0f);
+        d[8] = d[6] - 0.5f * (d[1] - d[3]) + 0.5f * mx - my * (1.0f / 6.0f);
+    } else if (side == 0) {
+        float s = d[0] + d[2] + d[4] + 2.0f * (d[3] + d[6] + d[7]);
+        drho = (s - 0.5f * gx + uwx) / (1.0f - uwx);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[1] = d[3] + (2.0f / 3.0f) * mx;
+        d[5] = d[7] - 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) + 0.5f * my;
+        d[8] = d[6] + 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) - 0.5f * my;
+    } else {
+        float s = d[0] + d[2] + d[4] + 2.0f * (d[1] + d[5] + d[8]);
+        drho = (s + 0.5f * gx - uwx) / (1.0f + uwx);
+        rho = 1.0f + drho;
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        d[3] = d[1] - (2.0f / 3.0f) * mx;
+        d[7] = d[5] + 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) - 0.5f * my;
+        d[6] = d[8] - 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) + 0.5f * my;
+    }
+}
+
+__device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float d[9]) {
+    if (c.bcy == 1) {
+        if (y == 0) zouhe_dev(2, d, c.f_uw[2][0], c.f_uw[2][1], c.f_g[0], c.f_g[1]);
+        else if (y == c.ny - 1) zouhe_dev(3, d, c.f_uw[3][0], c.f_uw[3][1], c.f_g[0], c.f_g[1]);
+    }
+    if (c.bcx == 1) {
+        if (x == 0) zouhe_dev(0, d, c.f_uw[0][0], c.f_uw[0][1], c.f_g[0], c.f_g[1]);
+        else if (x == c.nx - 1) zouhe_dev(1, d, c.f_uw[1][0], c.f_uw[1][1], c.f_g[0], c.f_g[1]);
+    }
+}
+
+// Streamed populations f^n at one node, as FP64 f_i (all forms).
+template <int ST>
+__device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c, int x, int y,
+                                              double f[9]) {
+    if constexpr (ST == ST_F64) {
+        const double* p = (const double*)fin;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int xs, ys;
+            pull_src(c, i, x, y, xs, ys);
+            f[i] = p[pidx(c, i, ys, xs)];
+        }
+        walls_f64(c, x, y, f);
+    } else {
+        using T = typename Sto<ST>::T;
+        const T* p = (const T*)fin;
+        float d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int xs, ys;
+            pull_src(c, i, x, y, xs, ys);
+            d[i] = load_dev<ST>(p, pidx(c, i, ys, xs), i, c);
+        }
+        walls_dev(c, x, y, d);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = wd(i) + (double)d[i];
+    }
+}
+
+// Moments of Eqs. (6), (7) before the IB force is known: rho and
+// j* = sum f e + g/2, summed over i in ascending order.
+__device__ __forceinline__ void moments_f64(const double f[9], const ChanDev& c, double& rho,
+                                            double& jx, double& jy) {
+    rho = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rho += f[i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) jx += f[i] * (double)ex(i);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) jy += f[i] * (double)ey(i);
+    jx += 0.5 * c.g[0];
+    jy += 0.5 * c.g[1];
+}
+
+// Force patches of a channel's particles covering node (x, y), summed in
+// ascending particle order.  Boxes hold wrapped origins on periodic axes.
+__device__ __forceinline__ void patch_force(const StepArgs& a, const ChanDev& c, int x, int y,
+                                            double& fx, double& fy) {
+    fx = 0.0;
+    fy = 0.0;
+    for (int q = c.p_begin; q < c.p_end; ++q) {
+        const PartDev& P = a.parts[q];
+        int dx = x - P.bx0, dy = y - P.by0;
+        if (c.bcx == 0 && dx < 0) dx += c.nx;
+        if (c.bcy == 0 && dy < 0) dy += c.ny;
+        if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
+            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            fx += v.x;
+            fy += v.y;
+        }
+    }
+}
+
+// The same sum over a short list of candidate particles (ascending).
+__device__ __forceinline__ void patch_force_list(const StepArgs& a, const ChanDev& c,
+                                                 const int* list, int n, int x, int y,
+                                                 double& fx, double& fy) {
+    fx = 0.0;
+    fy = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const PartDev& P = a.parts[list[j]];
+        int dx = x - P.bx0, dy = y - P.by0;
+        if (c.bcx == 0 && dx < 0) dx += c.nx;
+        if (c.bcy == 0 && dy < 0) dy += c.ny;
+        if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
+            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            fx += v.x;
+            fy += v.y;
+        }
+    }
+}
+
+// Do the boxes [x0, x0 + w) x [y0, y0 + h) and [u0, u0 + p) x [v0, v0 + q)
+// intersect?  Origins may be unwrapped; periodic axes compare modulo n.
+__device__ __forceinline__ bool span_overlap(int x0, int w, int u0, int p, int n, bool per) {
+    if (!per) return x0 < u0 + p && u0 < x0 + w;
+    if (w >= n || p >= n) return true;
+    int d1 = (u0 - x0) % n, d2 = (x0 - u0) % n;
+    if (d1 < 0) d1 += n;
+    if (d2 < 0) d2 += n;
+    return d1 < w || d2 < p;
+}
+
+__device__ __forceinline__ bool boxes_overlap(const ChanDev& c, int x0, int y0, int w, int h,
+                                              int u0, int v0, int p, int q) {
+    return span_overlap(x0, w, u0, p, c.nx, c.bcx == 0) && span_overlap(y0, h, v0, q, c.ny, c.bcy == 0);
+}
+
+// ---------------------------------------------------------------------------
+// MLS transfer operator (Sec. 1.2, Eqs. (8)-(10)) at one point, FP64.
+// 3x3 nodes around the nearest node (round half up); shifted linear basis
+// (1, x_k - x, y_k - y); nodes beyond a wall-bounded edge are dropped; the 3x3
+// moment matrix is inverted through its adjugate.  Outputs the anchor, the
+// validity mask and the value / x-derivative / y-derivative weights.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double kernel_weight(int kind, double r, double alpha) {
+    if (r > 1.0) return 0.0;
+    if (kind == 0) {
+        double q = r / alpha;
+        return exp(-(q * q));
+    } else if (kind == 1) {
+        return 2.0 / 3.0 - 4.0 * r * r + 4.0 * r * r * r;
+    } else if (kind == 2) {
+        return 1.0 - 6.0 * r * r + 8.0 * r * r * r - 3.0 * r * r * r * r;
+    }
+    return 0.25 * (1.0 + cos(3.14159265358979323846 / 2.0 * r));
+}
+
+__device__ __forceinline__ int wrapc(int v, int n, int periodic) {
+    if (!periodic) return v;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Box [x0, x0 + w) x [y0, y0 + h), in unwrapped lattice coordinates, that
+// holds every 3x3 stencil node of any point within `reach` of (X0, X1):
+// anchors round half up, plus one node on each side.
+__device__ __forceinline__ void stencil_box(double X0, double X1, double reach, int& x0, int& y0,
+                                            int& w, int& h) {
+    const double r = reach + 1e-6;
+    x0 = (int)floor(X0 - r + 0.5) - 1;
+    y0 = (int)floor(X1 - r + 0.5) - 1;
+    w = (int)floor(X0 + r + 0.5) + 2 - x0;
+    h = (int)floor(X1 + r + 0.5) + 2 - y0;
+}
+
+// Marker kinematics of Sec. 1.2: body-frame offset rotated by theta.
+struct Marker {
+    double rx, ry, xl, yl;
+    int i0, j0;
+};
+
+__device__ __forceinline__ Marker marker_at(const StepArgs& a, int idx, double X0, double X1,
+                                            double cs, double sn) {
+    Marker m;
+    const double2 x = a.xi[idx];
+    m.rx = cs * x.x - sn * x.y;
+    m.ry = sn * x.x + cs * x.y;
+    m.xl = X0 + m.rx;
+    m.yl = X1 + m.ry;
+    m.i0 = (int)floor(m.xl + 0.5);
+    m.j0 = (int)floor(m.yl + 0.5);
+    return m;
+}
+
+// Stencil node k of the 3x3 support around anchor (i0, j0): distance
+// components d = x_k - x, wrapped node, validity (beyond a wall-bounded edge
+// the node is dropped).
+__device__ __forceinline__ bool stencil_node(const ChanDev& c, int i0, int j0, int k, double x,
+                                             double y, double& dx, double& dy, int& ni, int& nj) {
+    const int ii = i0 + k % 3 - 1, jj = j0 + k / 3 - 1;
+    dx = (double)ii - x;
+    dy = (double)jj - y;
+    ni = wrapc(ii, c.nx, c.bcx == 0);
+    nj = wrapc(jj, c.ny, c.bcy == 0);
+    return (c.bcx == 0 || (ii >= 0 && ii < c.nx)) && (c.bcy == 0 || (jj >= 0 && jj < c.ny));
+}
+
+__device__ __forceinline__ bool node_valid(const ChanDev& c, int ii, int jj) {
+    return (c.bcx == 0 || (ii >= 0 && ii < c.nx)) && (c.bcy == 0 || (jj >= 0 && jj < c.ny));
+}
+
+__device__ __forceinline__ double stencil_weight(const ChanDev& c, double dx, double dy) {
+    const double r = sqrt(dx * dx + dy * dy) / c.rw;
+    return kernel_weight(c.kernel, r, c.alpha);
+}
+
+// Inverse (through the adjugate) of the moment matrix of Eq. (9), accumulated
+// over the valid nodes in ascending k from the weights in w[0..8].
+struct MlsInv {
+    double i00, i01, i02, i11, i12, i22;
+};
+
+__device__ __forceinline__ MlsInv mls_inverse(const ChanDev& c, const double* w, int i0, int j0,
+                                              double x, double y, bool all) {
+    double A00 = 0.0, A01 = 0.0, A02 = 0.0, A11 = 0.0, A12 = 0.0, A22 = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
+        if (!node_valid(c, ii, jj)) continue;
+        const double dx = (double)ii - x, dy = (double)jj - y, wk = w[q];
+        A00 += wk;
+        A01 += wk * dx;
+        A02 += wk * dy;
+        A11 += wk * dx * dx;
+        A12 += wk * dx * dy;
+        A22 += wk * dy * dy;
+    }
+    const double c00 = A11 * A22 - A12 * A12;
+    const double c01 = A02 * A12 - A01 * A22;
+    const double c02 = A01 * A12 - A02 * A11;
+    const double det = A00 * c00 + A01 * c01 + A02 * c02;
+    MlsInv r;
+    r.i00 = c00 / det;
+    r.i01 = c01 / det;
+    r.i02 = c02 / det;
+    r.i11 = r.i12 = r.i22 = 0.0;
+    if (all) {
+        const double c11 = A00 * A22 - A02 * A02;
+        const double c12 = A01 * A02 - A00 * A12;
+        const double c22 = A00 * A11 - A01 * A01;
+        r.i11 = c11 / det;
+        r.i12 = c12 / det;
+        r.i22 = c22 / det;
+    }
+    return r;
+}
+
+// Append this particle to the lists of the lattice tiles that its patch box
+// [x0, x0 + w) x [y0, y0 + h) (unwrapped coordinates) overlaps, so the
+// lattice pass looks up particle forces only there and only for listed
+// particles.  Periodic ranges split into at most two pieces.
+__device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, int x0, int y0,
+                                           int w, int h, int tid, int nthr) {
+    int xr[2][2], yr[2][2], nxr = 0, nyr = 0;
+    auto split = [](int lo, int len, int n, bool per, int r[2][2]) {
+        int cnt = 0;
+        if (per) {
+            int s0 = wrapc(lo, n, 1);
+            int e0 = s0 + len - 1;
+            if (e0 < n) {
+                r[0][0] = s0; r[0][1] = e0; cnt = 1;
+            } else {
+                r[0][0] = s0; r[0][1] = n - 1; r[1][0] = 0; r[1][1] = e0 - n; cnt = 2;
+            }
+        } else {
+            int s0 = max(lo, 0), e0 = min(lo + len - 1, n - 1);
+            if (s0 <= e0) { r[0][0] = s0; r[0][1] = e0; cnt = 1; }
+        }
+        return cnt;
+    };
+    nxr = split(x0, w, c.nx, c.bcx == 0, xr);
+    nyr = split(y0, h, c.ny, c.bcy == 0, yr);
+    int* tl = a.tlist + (long long)a.parity * a.ntiles * kTileList;
+    for (int p = 0; p < nxr; ++p)
+        for (int q = 0; q < nyr; ++q) {
+            const int tx0 = xr[p][0] / a.tile_w, tx1 = xr[p][1] / a.tile_w;
+            const int ty0 = yr[q][0] / a.tile_h, ty1 = yr[q][1] / a.tile_h;
+            const int ntx = tx1 - tx0 + 1, cnt = ntx * (ty1 - ty0 + 1);
+            for (int t = tid; t < cnt; t += nthr) {
+                int* e = tl + (long long)(c.tile0 + (ty0 + t / ntx) * c.tiles_x + tx0 + t % ntx) * kTileList;
+                const int slot = atomicAdd(e, 1);
+                if (slot < kTileList - 1) e[1 + slot] = (int)blockIdx.x;
+            }
+        }
+}
+
+}  // namespace lbmk

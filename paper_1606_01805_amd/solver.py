@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PSTATE, check, lib
+from ._lib import AGRAD, PSTATE, check, lib
 
 _CFG_DEFAULTS = dict(
     tau=1.0, bc_x=0, bc_y=0, u_wall=((0.0, 0.0),) * 4, init=0, body_force=(0.0, 0.0),
@@ -84,6 +84,7 @@ class Solver:
         self._h = h
         self.n_particles = 0
         self.particle_channel = []
+        self._nmarkers = []
         for ci, (_, parts) in enumerate(channels):
             for p in parts:
                 self.add_particle(ci, p)
@@ -116,6 +117,7 @@ class Solver:
         self._chk(self._L.lbm_add_particle(self._h, int(channel), ctypes.byref(desc), ctypes.byref(pid)))
         self.n_particles += 1
         self.particle_channel.append(channel)
+        self._nmarkers.append(int(xi.shape[0]))
         return pid.value
 
     # -- stepping --
@@ -174,3 +176,39 @@ class Solver:
     @property
     def steps_done(self):
         return int(self._L.lbm_steps_done(self._h))
+
+    # -- adjoint --
+    def adjoint_begin(self, seed, max_segment):
+        """Start reverse mode at the current step; seed [n_particles, 10] is
+        dJ/d(last particle records)."""
+        seed = _f64(seed, (self.n_particles, PSTATE)) if self.n_particles else np.zeros((1, PSTATE))
+        self._chk(self._L.lbm_adjoint_begin(self._h, _p(seed), int(max_segment)))
+
+    def adjoint_segment(self, slot, n):
+        """Reverse the n steps that start at checkpoint `slot`."""
+        self._chk(self._L.lbm_adjoint_segment(self._h, int(slot), int(n)))
+
+    @property
+    def adjoint_position(self):
+        return int(self._L.lbm_adjoint_position(self._h))
+
+    def adjoint_gradients(self):
+        """(part [n_particles, 17], markers: list of [n_markers, 5] per
+        particle, wall [n_channels, 4, 2])."""
+        npart = self.n_particles
+        part = np.zeros((max(npart, 1), AGRAD))
+        nmk = sum(self._nmarkers)
+        mk = np.zeros((max(nmk, 1), 5))
+        wall = np.zeros((len(self.cfgs), 4, 2))
+        self._chk(self._L.lbm_adjoint_gradients(self._h, _p(part), _p(mk), _p(wall)))
+        out, o = [], 0
+        for m in self._nmarkers:
+            out.append(mk[o:o + m].copy())
+            o += m
+        return part[:npart], out, wall
+
+    def adjoint_field(self, channel=0):
+        c = self.cfgs[channel]
+        f = np.zeros((9, c["ny"], c["nx"]))
+        self._chk(self._L.lbm_adjoint_field(self._h, channel, _p(f)))
+        return f

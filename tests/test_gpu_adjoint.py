@@ -1,0 +1,219 @@
+"""Discrete adjoint of the coupled step on the GPU, through the C ABI, against
+central finite differences of the FP64 oracle.
+
+J = c . (x, y, theta, u, v, omega) after T steps, c random.  Every gradient
+the library returns is checked: initial pose and velocities (the BDF2
+history starts equal to them, so each is the sum of its current and previous
+slots at step 0), marker positions, normals and segment lengths, area and
+polar moment (through m = ratio * area, I = ratio * polar moment), wall
+velocities (Zou-He closure and Couette start) and, through the adjoint
+populations, a random interior perturbation of the initial populations.
+The finite differences are Richardson-extrapolated and taken only where the
+MLS anchors of all perturbed runs agree (tests/adjoint_fd.py); their
+accuracy is ~1e-10 relative, so the FP64 bar is 1e-6 relative plus 5e-11
+absolute (J is of order 10: 5e-12 of it).
+"""
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from workloads import shapes
+
+import adjoint_fd as FD
+
+pytestmark = pytest.mark.gpu
+
+TOL_R, TOL_A = 1e-6, 5e-11
+
+
+def _case(kind):
+    if kind == "couette":
+        cfg = C.couette_config(32, 24, tau=0.8, storage=0)
+    elif kind == "sidewall":
+        cfg = C.base_config(24, 32, tau=0.8, bc_x=1, u_wall=[[0.0, 0.01], [0.0, -0.02], [0.0, 0.0], [0.0, 0.0]],
+                            body_force=[0.0, 1e-5], storage=0)
+    elif kind == "cosine-unit":
+        cfg = C.couette_config(32, 24, tau=0.8, storage=0, mls_kernel=3, spread_scale=1)
+    else:
+        raise ValueError(kind)
+    cfg["gravity"] = [0.0, -1e-5]
+    sh = shapes.ellipse(8.0, 2.0, n_markers=20, mode="param")
+    p = C.particle(sh, 15.3, 11.1, 0.3, density_ratio=1.3, u=0.002, v=-0.001, omega=0.001)
+    return cfg, [p]
+
+
+def gpu_adjoint(cfg, parts, T, c, seg=None, storage=None, tuning=None):
+    from paper_1606_01805_amd import Solver
+
+    seg = seg or T
+    s = Solver([(cfg, parts)], storage=storage, tuning=tuning)
+    for k in range(T // seg):
+        s.checkpoint_save(k)
+        s.step(seg, record=False)
+    seed = np.zeros((1, 10))
+    seed[0, :6] = c
+    s.adjoint_begin(seed, seg)
+    for k in reversed(range(T // seg)):
+        s.adjoint_segment(k, seg)
+    assert s.adjoint_position == 0
+    part, mk, wall = s.adjoint_gradients()
+    lam = s.adjoint_field(0)
+    s.close()
+    return part[0], mk[0], wall[0], lam
+
+
+def _params(cfg, parts, part, mk, wall):
+    ratio = parts[0]["density_ratio"]
+    rows = [("x0", part[0] + part[2], FD.particle_field("x")),
+            ("y0", part[1] + part[3], FD.particle_field("y")),
+            ("theta0", part[4] + part[5], FD.particle_field("theta")),
+            ("u0", part[6] + part[8], FD.particle_field("u")),
+            ("v0", part[7] + part[9], FD.particle_field("v")),
+            ("omega0", part[10] + part[11], FD.particle_field("omega")),
+            ("area", part[15] * ratio, FD.particle_field("area")),
+            ("polar", part[16] * ratio, FD.particle_field("polar_moment"))]
+    for l in (0, 7, 13):
+        rows += [(f"xi[{l}].x", mk[l, 0], FD.particle_field("xi", 2 * l)),
+                 (f"xi[{l}].y", mk[l, 1], FD.particle_field("xi", 2 * l + 1)),
+                 (f"nrm[{l}].x", mk[l, 2], FD.particle_field("nrm", 2 * l)),
+                 (f"nrm[{l}].y", mk[l, 3], FD.particle_field("nrm", 2 * l + 1)),
+                 (f"ds[{l}]", mk[l, 4], FD.particle_field("ds", l))]
+    sides = (2, 3) if cfg["bc_y"] == 1 else ((0, 1) if cfg["bc_x"] == 1 else ())
+    for sd in sides:
+        for comp in (0, 1):
+            rows.append((f"u_wall[{sd}][{comp}]", wall[sd, comp], FD.wall_speed(sd, comp)))
+    return rows
+
+
+@pytest.mark.parametrize("kind", ["couette", "sidewall", "cosine-unit"])
+def test_adjoint_matches_oracle_finite_differences(kind):
+    cfg, parts = _case(kind)
+    T = 12
+    c = np.random.default_rng(11).standard_normal(6)
+    part, mk, wall, lam = gpu_adjoint(cfg, parts, T, c)
+    bad = []
+    for name, g, pert in _params(cfg, parts, part, mk, wall):
+        fd, h = FD.derivative(cfg, parts, T, c, pert)
+        assert fd is not None, f"{name}: anchors change for every step size"
+        err = abs(g - fd)
+        print(f"{kind} {name:14s} adjoint {g: .12e} fd {fd: .12e} (h={h:g}) err {err:.2e}")
+        if err > TOL_R * abs(fd) + TOL_A:
+            bad.append((name, g, fd))
+    # dJ/d(initial populations) along an interior direction
+    o_f0 = _oracle_f0(cfg, parts)
+    d = np.random.default_rng(3).standard_normal(o_f0.shape) * 1e-2
+    if cfg["bc_y"] == 1:
+        d[:, 0, :] = d[:, -1, :] = 0.0
+    if cfg["bc_x"] == 1:
+        d[:, :, 0] = d[:, :, -1] = 0.0
+
+    def pert_f(cf, pp, eps):
+        return o_f0 + eps * d
+
+    fd, h = FD.derivative(cfg, parts, T, c, pert_f)
+    g = float((lam * d).sum())
+    print(f"{kind} {'f0 direction':14s} adjoint {g: .12e} fd {fd: .12e} (h={h:g})")
+    if abs(g - fd) > TOL_R * abs(fd) + TOL_A:
+        bad.append(("f0", g, fd))
+    assert not bad, bad
+
+
+def _oracle_f0(cfg, parts):
+    import oracle
+
+    o = oracle.Oracle(cfg)
+    for p in parts:
+        o.add_particle(p)
+    return o.populations()
+
+
+def test_segments_reproduce_single_sweep_bitwise():
+    cfg, parts = _case("couette")
+    c = np.random.default_rng(5).standard_normal(6)
+    a = gpu_adjoint(cfg, parts, 12, c)
+    b = gpu_adjoint(cfg, parts, 12, c, seg=4)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_adjoint_launch_shape_independent():
+    cfg, parts = _case("couette")
+    c = np.random.default_rng(6).standard_normal(6)
+    a = gpu_adjoint(cfg, parts, 8, c)
+    b = gpu_adjoint(cfg, parts, 8, c, tuning=dict(tile_w=64, rows_per_thread=2))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 1e-3), (C.STORE_F16S, 3e-2)])
+def test_reduced_forms_close_to_fp64_adjoint(storage, tol):
+    """FP32 / FP16S populations (FP32 adjoint populations): each gradient
+    group within tol of the FP64 adjoint, relative to the group's largest
+    entry."""
+    cfg, parts = _case("couette")
+    c = np.random.default_rng(7).standard_normal(6)
+    ref = gpu_adjoint(cfg, parts, 12, c)
+    red = gpu_adjoint(cfg, parts, 12, c, storage=storage)
+    for name, x, y in zip(("particle", "markers", "walls", "populations"), ref, red):
+        e = np.abs(x - y).max() / np.abs(x).max()
+        print(storage, name, e)
+        assert e < tol, (name, e)
+
+
+# ---------------------------------------------------------------------------
+# The 256x64 Couette case through torch.autograd, against the committed
+# finite differences of the FP64 oracle (tests/golden/make_adjoint_golden.py).
+# ---------------------------------------------------------------------------
+def _couette_256x64(storage):
+    import json
+    import os
+
+    import torch
+
+    from paper_1606_01805_amd.autograd import RunSpec, run_particles
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint_couette_256x64_fd.json")))
+    b = gold["base"]
+    f64 = torch.float64
+    y0, th0, AR, U = (torch.tensor(b[k], dtype=f64, requires_grad=True) for k in ("y0", "theta0", "AR", "U"))
+    sh = shapes.ellipse(16.0, AR, n_markers=40, mode="param")
+    z = torch.zeros((), dtype=f64)
+    pose = torch.stack([torch.tensor(128.0, dtype=f64), y0, th0, z, z, z])[None]
+    u_wall = torch.stack([torch.stack([z, z]), torch.stack([z, z]), torch.stack([-U, z]), torch.stack([U, z])])[None]
+    cfg = C.adjoint_case(storage=storage).channels[0][0]
+    spec = RunSpec(configs=[cfg], density_ratio=[1.0], n_markers=[40], channel=[0], steps=gold["steps"],
+                   segment=100, storage=storage)
+    out = run_particles(pose, sh["xi"], sh["nrm"], sh["ds"], sh["area"].reshape(1), sh["polar_moment"].reshape(1),
+                        u_wall, spec)
+    gy = torch.autograd.grad(out[0, 1], [y0, th0, AR, U], retain_graph=True)
+    gw = torch.autograd.grad(out[0, 5], [y0, th0, AR, U])
+    spec.solver.close()
+    return gold, out.detach().numpy(), [float(v) for v in gy], [float(v) for v in gw]
+
+
+@pytest.mark.parametrize("storage,tol", [(C.STORE_F64, 1e-5), (C.STORE_F32, 5e-3)])
+def test_couette_256x64_gradients_match_oracle_fd(storage, tol):
+    """d y(T) and d omega(T) (T = 2000, 20 checkpointed segments of 100) with
+    respect to y0, theta0, aspect ratio and wall speed.
+
+    Bar: tol relative plus twice the finite difference's own error estimate
+    |D(h) - D(h/2)| = 3/4 |D(h) - R| (R the Richardson value): over 2000
+    steps the rounding noise of J divided by the small h the anchors allow
+    reaches ~1e-5 of the smaller derivatives.  tol = 1e-5 for FP64
+    populations; 5e-3 for FP32 populations, where the forward map itself is
+    the rounded one (measured worst 2.2e-3, d omega / d y0)."""
+    gold, out, gy, gw = _couette_256x64(storage)
+    print("final", out[0, :6], "oracle y", gold["y"], "omega", gold["omega"])
+    bad = []
+    for k, name in enumerate(("y0", "theta0", "AR", "U")):
+        g = gold["grad"][name]
+        assert g is not None, name
+        for key, val in (("y", gy[k]), ("omega", gw[k])):
+            ref = g[key]
+            unc = 0.75 * abs(g[key + "_central_h"] - ref)
+            err = abs(val - ref) / abs(ref)
+            print(f"{storage} d{key}/d{name}: adjoint {val: .10e} fd {ref: .10e} (h={g['h']:g}) rel {err:.2e}"
+                  f" fd-unc {unc / abs(ref):.1e}")
+            if abs(val - ref) > tol * abs(ref) + 2 * unc:
+                bad.append((key, name, val, ref, err))
+    assert not bad, bad
