@@ -25,24 +25,36 @@
 // Field arithmetic is FP64; the adjoint populations are stored in FP64 for the
 // FP64 form and in FP32 otherwise.  Every sum has a fixed order (no float
 // atomics), so the adjoint is bitwise reproducible.
+#include <climits>
+
 #include "lbm_device.h"
 
 namespace lbmk {
+
+// The particle kernels of the adjoint hold more live FP64 state per thread
+// than the forward ones: they run 56 markers x 9 stencil nodes per round in
+// 512-thread workgroups (two waves per SIMD, 256 VGPRs each, no spills).
+constexpr int kAdjRound = 56;
+constexpr int kAdjThreads = 512;
+// Patch cells of an adjoint box that the deposit can index by anchor masks
+// (64-bit, one bit per marker of a round); larger boxes scan the markers.
+constexpr int kAdjMaskCells = 4096;
 
 template <int ST> struct LamT { using T = float; };
 template <> struct LamT<ST_F64> { using T = double; };
 
 // Adjoint of the population i pulled at (x, y) by the next step: the pull
 // read the node x - e_i, so its adjoint is read at x + e_i.  Beyond a
-// wall-bounded edge nothing was pulled: zero.
+// wall-bounded edge nothing was pulled: zero.  Branch-free (the address is
+// clamped to a valid node and the value masked), so the nine reads of a node
+// are issued together.
 template <int ST>
 __device__ __forceinline__ double lam_push(const void* lam, const ChanDev& c, int i, int x, int y) {
-    int xd = x + ex(i), yd = y + ey(i);
-    if (c.bcx == 0) xd = xd < 0 ? xd + c.nx : (xd >= c.nx ? xd - c.nx : xd);
-    else if (xd < 0 || xd >= c.nx) return 0.0;
-    if (c.bcy == 0) yd = yd < 0 ? yd + c.ny : (yd >= c.ny ? yd - c.ny : yd);
-    else if (yd < 0 || yd >= c.ny) return 0.0;
-    return (double)((const typename LamT<ST>::T*)lam)[pidx(c, i, yd, xd)];
+    const int xd = x + ex(i), yd = y + ey(i);
+    const int xs = pull_coord(xd, x, c.nx, c.bcx == 0), ys = pull_coord(yd, y, c.ny, c.bcy == 0);
+    const bool ok = (c.bcx == 0 || (xd >= 0 && xd < c.nx)) && (c.bcy == 0 || (yd >= 0 && yd < c.ny));
+    const double v = (double)((const typename LamT<ST>::T*)lam)[pidx(c, i, ys, xs)];
+    return ok ? v : 0.0;
 }
 
 // Streamed populations at (x, y) before any wall closure, FP64.
@@ -76,61 +88,14 @@ __device__ __forceinline__ double kernel_dw(int kind, double r, double alpha) {
     return -0.25 * h * sin(h * r) / r;
 }
 
-// d/d(x, y) of sum_k lam_k . (phi_k, Dx_k, Dy_k), the MLS value and
-// derivative weights of Eq. (8) at the point (x, y), anchors held fixed.
-// With B = A^{-1}, z_k = B p_k, y_k = B lam_k and S = sum_k W_k z_k y_k^T:
-//   d/dx_b = sum_k dW_k/dx_b (lam_k . z_k - p_k^T S p_k)
-//          + sum_k W_k ((S^T p_k)_b + (S p_k)_b) - sum_k W_k (y_k)_b,
-// b the x or y slot of p (dp_k/dx_b = -e_b).
-__device__ __forceinline__ void mls_point_adj(const ChanDev& c, const double* w, const MlsInv& iv, int i0, int j0,
-                              double x, double y, const double (*lam)[3], double& ox, double& oy) {
-    const double B[3][3] = {{iv.i00, iv.i01, iv.i02}, {iv.i01, iv.i11, iv.i12}, {iv.i02, iv.i12, iv.i22}};
-    double S[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-        if (!node_valid(c, ii, jj)) continue;
-        const double p[3] = {1.0, (double)ii - x, (double)jj - y};
-        double z[3], yv[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            z[r] = B[r][0] * p[0] + B[r][1] * p[1] + B[r][2] * p[2];
-            yv[r] = B[r][0] * lam[q][0] + B[r][1] * lam[q][1] + B[r][2] * lam[q][2];
-        }
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) S[r][s] += w[q] * z[r] * yv[s];
-    }
-    const double irw2 = 1.0 / (c.rw * c.rw);
-    ox = 0.0;
-    oy = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-        if (!node_valid(c, ii, jj)) continue;
-        const double dx = (double)ii - x, dy = (double)jj - y;
-        const double p[3] = {1.0, dx, dy};
-        double z[3], yv[3], Sp[3], STp[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            z[r] = B[r][0] * p[0] + B[r][1] * p[1] + B[r][2] * p[2];
-            yv[r] = B[r][0] * lam[q][0] + B[r][1] * lam[q][1] + B[r][2] * lam[q][2];
-            Sp[r] = S[r][0] * p[0] + S[r][1] * p[1] + S[r][2] * p[2];
-            STp[r] = S[0][r] * p[0] + S[1][r] * p[1] + S[2][r] * p[2];
-        }
-        const double lz = lam[q][0] * z[0] + lam[q][1] * z[1] + lam[q][2] * z[2];
-        const double pSp = p[0] * Sp[0] + p[1] * Sp[1] + p[2] * Sp[2];
-        const double r = sqrt(dx * dx + dy * dy) / c.rw;
-        const double dw = kernel_dw(c.kernel, r, c.alpha);
-        ox += -dw * dx * irw2 * (lz - pSp) + w[q] * (STp[1] + Sp[1]) - w[q] * yv[1];
-        oy += -dw * dy * irw2 * (lz - pSp) + w[q] * (STp[2] + Sp[2]) - w[q] * yv[2];
-    }
-}
-
 // Transpose of the forced collision of one node (Eqs. (4), (5)) at (rho, u, G)
 // applied to the adjoint lfc of its outputs: the feq part of d/d rho, d/d u
-// and d/d G.
+// and d/d G.  Every term is linear in the weighted moments of lfc,
+// A0 = sum w_i a_i, A_a = sum w_i a_i e_ia, A_ab = sum w_i a_i e_ia e_ib,
+// because feq and the Guo term are polynomials in e_i of degree two:
+//   d/d rho = (A0 (1 - 1.5 u.u) + 3 u.A1 + 4.5 u.A2.u) / tau
+//   d/d u   = rho/tau (3 A1 + 9 A2 u - 3 u A0) + pref (9 A2 G - 3 G A0)
+//   d/d G   = pref (3 A1 - 3 u A0 + 9 A2 u)
 struct CollAdj {
     double lrho, lux, luy, lGx, lGy;
 };
@@ -139,18 +104,25 @@ __device__ __forceinline__ CollAdj collide_adj(const double lfc[9], double rho, 
                                                double Gx, double Gy, double tau) {
     const double pref = 1.0 - 1.0 / (2.0 * tau);
     const double itau = 1.0 / tau;
+    // e: 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1) 6 (-1,1) 7 (-1,-1) 8 (1,-1)
+    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+    const double ax = lfc[1] + lfc[3], ay = lfc[2] + lfc[4];
+    const double dg = lfc[5] + lfc[6] + lfc[7] + lfc[8];
+    const double A0 = w0 * lfc[0] + w1 * (ax + ay) + w2 * dg;
+    const double Ax = w1 * (lfc[1] - lfc[3]) + w2 * ((lfc[5] - lfc[6]) + (lfc[8] - lfc[7]));
+    const double Ay = w1 * (lfc[2] - lfc[4]) + w2 * ((lfc[5] + lfc[6]) - (lfc[7] + lfc[8]));
+    const double Axx = w1 * ax + w2 * dg;
+    const double Ayy = w1 * ay + w2 * dg;
+    const double Axy = w2 * ((lfc[5] + lfc[7]) - (lfc[6] + lfc[8]));
     const double usq = ux * ux + uy * uy;
-    CollAdj r{0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const double exi = (double)ex(i), eyi = (double)ey(i), w = wd(i), a = lfc[i];
-        const double eu = exi * ux + eyi * uy, eg = exi * Gx + eyi * Gy;
-        r.lrho += a * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq) * itau;
-        r.lux += a * (w * rho * (3.0 * exi + 9.0 * eu * exi - 3.0 * ux) * itau + pref * w * (-3.0 * Gx + 9.0 * exi * eg));
-        r.luy += a * (w * rho * (3.0 * eyi + 9.0 * eu * eyi - 3.0 * uy) * itau + pref * w * (-3.0 * Gy + 9.0 * eyi * eg));
-        r.lGx += a * pref * w * (3.0 * (exi - ux) + 9.0 * eu * exi);
-        r.lGy += a * pref * w * (3.0 * (eyi - uy) + 9.0 * eu * eyi);
-    }
+    const double A2u_x = Axx * ux + Axy * uy, A2u_y = Axy * ux + Ayy * uy;
+    const double A2G_x = Axx * Gx + Axy * Gy, A2G_y = Axy * Gx + Ayy * Gy;
+    CollAdj r;
+    r.lrho = (A0 * (1.0 - 1.5 * usq) + 3.0 * (ux * Ax + uy * Ay) + 4.5 * (ux * A2u_x + uy * A2u_y)) * itau;
+    r.lux = rho * itau * (3.0 * Ax + 9.0 * A2u_x - 3.0 * ux * A0) + pref * (9.0 * A2G_x - 3.0 * Gx * A0);
+    r.luy = rho * itau * (3.0 * Ay + 9.0 * A2u_y - 3.0 * uy * A0) + pref * (9.0 * A2G_y - 3.0 * Gy * A0);
+    r.lGx = pref * (3.0 * Ax - 3.0 * ux * A0 + 9.0 * A2u_x);
+    r.lGy = pref * (3.0 * Ay - 3.0 * uy * A0 + 9.0 * A2u_y);
     return r;
 }
 
@@ -224,6 +196,36 @@ __device__ __forceinline__ void zouhe_adj(int side, const double fr[9], double L
     }
 }
 
+// Inverse of the MLS moment matrix (as mls_inverse) with one reciprocal of
+// the determinant: the adjoint linearises the step at the taped state, where
+// the last bits of B do not matter.
+__device__ __forceinline__ MlsInv mls_inverse_adj(const ChanDev& c, const double* w, int i0, int j0, double x,
+                                                  double y) {
+    double A00 = 0.0, A01 = 0.0, A02 = 0.0, A11 = 0.0, A12 = 0.0, A22 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
+        if (!node_valid(c, ii, jj)) continue;
+        const double dx = (double)ii - x, dy = (double)jj - y, wk = w[q];
+        A00 += wk;
+        A01 += wk * dx;
+        A02 += wk * dy;
+        A11 += wk * dx * dx;
+        A12 += wk * dx * dy;
+        A22 += wk * dy * dy;
+    }
+    const double c00 = A11 * A22 - A12 * A12, c01 = A02 * A12 - A01 * A22, c02 = A01 * A12 - A02 * A11;
+    const double idet = 1.0 / (A00 * c00 + A01 * c01 + A02 * c02);
+    MlsInv r;
+    r.i00 = c00 * idet;
+    r.i01 = c01 * idet;
+    r.i02 = c02 * idet;
+    r.i11 = (A00 * A22 - A02 * A02) * idet;
+    r.i12 = (A01 * A02 - A00 * A12) * idet;
+    r.i22 = (A00 * A11 - A01 * A01) * idet;
+    return r;
+}
+
 // Cell of the box (wrapped origin x0, y0, extent w x h) holding node (x, y),
 // or -1.
 __device__ __forceinline__ int box_cell(const ChanDev& c, int x0, int y0, int w, int h, int x, int y) {
@@ -266,6 +268,39 @@ __device__ __forceinline__ void patch_terms(const AdjArgs& a, const ChanDev& c, 
     }
 }
 
+// Boxes of the neighbour particles' force and adjoint patches, staged in LDS
+// so that a node's patch addresses are known as soon as the node is, and the
+// patch reads go out together with the population reads.
+struct NbBox {
+    int fx0, fy0, fw, fh;    // force patch (fw = 0: none)
+    int ax0, ay0, aw, ah;    // adjoint patch (aw = 0: none)
+    long long foff, aoff;
+};
+
+template <int NF>
+__device__ __forceinline__ void patch_terms_lds(const AdjArgs& a, const ChanDev& c, const NbBox* nb, int n, int x,
+                                                int y, double& fx, double& fy, double t[kAdjCell]) {
+    fx = 0.0;
+    fy = 0.0;
+#pragma unroll
+    for (int k = 0; k < kAdjCell; ++k) t[k] = 0.0;
+    // reads from clamped (always allocated) cells, masked: no load waits on
+    // a branch
+    for (int j = 0; j < n; ++j) {
+        const NbBox& B = nb[j];
+        const int cf = box_cell(c, B.fx0, B.fy0, B.fw, B.fh, x, y);
+        const double2 v = a.s.patch[B.foff + (cf >= 0 ? cf : 0)];
+        fx += cf >= 0 ? v.x : 0.0;
+        fy += cf >= 0 ? v.y : 0.0;
+        if (NF > 0) {
+            const int ca = box_cell(c, B.ax0, B.ay0, B.aw, B.ah, x, y);
+            const double* va = a.apatch + (B.aoff + (ca >= 0 ? ca : 0)) * kAdjCell;
+#pragma unroll
+            for (int k = 0; k < NF; ++k) t[k] += ca >= 0 ? va[k] : 0.0;
+        }
+    }
+}
+
 // Force f_lb alone at (x, y) from a list of forward patches (ascending).
 __device__ __forceinline__ void fwd_force(const AdjArgs& a, const ChanDev& c, const int* list, int n,
                                           int x, int y, double& fx, double& fy) {
@@ -287,17 +322,129 @@ __device__ __forceinline__ void fwd_force(const AdjArgs& a, const ChanDev& c, co
 }
 
 // ---------------------------------------------------------------------------
+// Motion of the MLS weights with the evaluation point x, anchors held fixed.
+// Psi_k = (phi_k, Dx_k, Dy_k) = W_k B p_k are the value and derivative
+// weights of Eq. (8) (B = A^{-1}, p_k = (1, x_k - x)).  With z_k = B p_k,
+// y_k = B lam_k and S = sum_k W_k z_k y_k^T,
+//   d/dx_b sum_k lam_k . Psi_k = sum_k dW_k/dx_b (lam_k . z_k - p_k^T S p_k)
+//                              + sum_k W_k ((S^T p_k)_b + (S p_k)_b - (y_k)_b)
+// (b the x or y slot of p; dp_k/dx_b = -e_b).  Split over the nine stencil
+// threads of a marker: each leaves its share of S, the shares are summed,
+// then each forms its term.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mls_share(const double* B6, const double p[3], const double lam[3], double w,
+                                          double z[3], double y[3], double* S9) {
+    const double B[3][3] = {{B6[0], B6[1], B6[2]}, {B6[1], B6[3], B6[4]}, {B6[2], B6[4], B6[5]}};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        z[r] = B[r][0] * p[0] + B[r][1] * p[1] + B[r][2] * p[2];
+        y[r] = B[r][0] * lam[0] + B[r][1] * lam[1] + B[r][2] * lam[2];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S9[3 * r + q] = w * z[r] * y[q];
+}
+
+__device__ __forceinline__ void mls_term(const ChanDev& c, const double* S9, const double p[3], const double z[3],
+                                         const double y[3], const double lam[3], double w, double& ox, double& oy) {
+    double Sp[3], STp[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        Sp[r] = S9[3 * r] * p[0] + S9[3 * r + 1] * p[1] + S9[3 * r + 2] * p[2];
+        STp[r] = S9[r] * p[0] + S9[3 + r] * p[1] + S9[6 + r] * p[2];
+    }
+    const double lz = lam[0] * z[0] + lam[1] * z[1] + lam[2] * z[2];
+    const double pSp = p[0] * Sp[0] + p[1] * Sp[1] + p[2] * Sp[2];
+    const double dx = p[1], dy = p[2];
+    const double r = sqrt(dx * dx + dy * dy) / c.rw;
+    const double dw = kernel_dw(c.kernel, r, c.alpha) / (c.rw * c.rw);
+    ox = -dw * dx * (lz - pSp) + w * (STp[1] + Sp[1]) - w * y[1];
+    oy = -dw * dy * (lz - pSp) + w * (STp[2] + Sp[2]) - w * y[2];
+}
+
+// Deposit the round's per-(marker, node) terms d[m * 9 + k][0..NF) into the
+// particle's adjoint patch (fields F0..F0+NF): each cell sums the markers
+// whose stencils cover it in ascending order (found from the anchor masks of
+// its 3x3 neighbourhood, or by a scan when the box is larger than the mask
+// store); a cell is handled by the same thread in every round.  The first
+// round writes the cell (and zeroes fields NZ.. when NZ < kAdjCell), later
+// rounds add to it.
+template <int NF, int F0, int W, int NZ>
+__device__ __forceinline__ void deposit_round(double* apatch, int ax0u, int ay0u, int aw, int ah, int ncell,
+                                              const int2* anc, const unsigned long long* mask,
+                                              const double (*d)[W], int nr, bool first) {
+    const bool masked = ncell <= kAdjMaskCells;
+    for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+        const int qx = q % aw, qy = q / aw;
+        const int cx = ax0u + qx, cy = ay0u + qy;
+        double t[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) t[f] = 0.0;
+        if (masked) {
+            unsigned long long msk = 0ull;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = qy + dy;
+                if (yy < 0 || yy >= ah) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = qx + dx;
+                    if (xx < 0 || xx >= aw) continue;
+                    msk |= mask[yy * aw + xx];
+                }
+            }
+            while (msk) {
+                const int m = __ffsll((long long)msk) - 1;
+                msk &= msk - 1ull;
+                const int2 an = anc[m];
+                const int kk = 3 * (cy - an.y + 1) + (cx - an.x + 1);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) t[f] += d[m * 9 + kk][f];
+            }
+        } else {
+            for (int m = 0; m < nr; ++m) {
+                const int2 an = anc[m];
+                const int ddx = cx - an.x, ddy = cy - an.y;
+                if (ddx < -1 || ddx > 1 || ddy < -1 || ddy > 1) continue;
+                const int kk = 3 * (ddy + 1) + (ddx + 1);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) t[f] += d[m * 9 + kk][f];
+            }
+        }
+        double* v = apatch + (long long)q * kAdjCell;
+        if (first) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[F0 + f] = t[f];
+#pragma unroll
+            for (int f = NZ; f < kAdjCell; ++f) v[f] = 0.0;
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[F0 + f] += t[f];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Kernel A: transpose of BDF2 and of the surface-stress force (one workgroup
 // per particle, markers in rounds of 64, one thread per (marker, probe
 // stencil node)).
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
-    __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
-    __shared__ double s_dep[kIbmThreads][3];
-    __shared__ int2 s_anc[kRound];
-    __shared__ double s_part[AL_N], s_lF[3], s_sum[8];
+__global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
+    __shared__ double s_w[kAdjThreads], s_r[kAdjThreads], s_ux[kAdjThreads], s_uy[kAdjThreads];
+    __shared__ double s_dep[kAdjThreads][3];
+    __shared__ double s_S[kAdjThreads][9];  // per node: share of S, then its term
+    __shared__ double s_Sm[kAdjRound][9];
+    __shared__ double s_B[kAdjRound][6];
+    __shared__ double s_sc[kAdjRound][5];      // d/d rho_P, d/d (du/dx, du/dy, dv/dx, dv/dy)
+    __shared__ double s_xp[kAdjRound][2];
+    __shared__ double s_geo[kAdjRound][4];     // r and n of the marker
+    __shared__ double s_g[kAdjRound][5];       // its accumulated shape gradients
+    __shared__ double s_pt[kAdjRound][8];      // its particle terms
+    __shared__ int2 s_anc[kAdjRound];
+    __shared__ double s_part[AL_N], s_lF[3], s_run[8];
     __shared__ int s_nb[kMaxNeighbours], s_nnb;
+    __shared__ NbBox s_box[kMaxNeighbours];
+    __shared__ unsigned long long s_mask[kAdjMaskCells];
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     if (b >= a.s.nparts) return;
@@ -305,8 +452,15 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
     AdjPart* A = a.ap + b;
     const ChanDev& c = a.s.chan[P->chan];
     const int nm = P->nm, mb = P->mbeg;
+    // marker geometry of the first round, requested before anything else
+    double2 pre_x = make_double2(0.0, 0.0), pre_n = make_double2(0.0, 0.0);
+    if (tid / 9 < kAdjRound && tid / 9 < nm) {
+        pre_x = a.s.xi[mb + tid / 9];
+        pre_n = a.s.nrm[mb + tid / 9];
+    }
     const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
     const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
+    if (tid < 8) s_run[tid] = 0.0;
     const double nu = c.nu, dn = c.dn;
     const double cs = cos(th), sn = sin(th);
 
@@ -314,9 +468,10 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
     int ax0u, ay0u, aw, ah;
     stencil_box(X0, X1, P->rb + dn, ax0u, ay0u, aw, ah);
     const bool fits = (long long)aw * ah <= A->acap && aw <= c.nx && ah <= c.ny;
-    if (tid == 0) {
+    if (tid == 64) {
         // BDF2 transpose (Eqs. (15), (16) with the position update): the
         // adjoint of the new velocity collects that of the new position.
+        // (First lane of the second wave: overlaps the neighbour scan.)
         const double* Ln = A->l;
         const double lV1x = Ln[AL_V] + 2.0 / 3.0 * Ln[AL_X];
         const double lV1y = Ln[AL_V + 1] + 2.0 / 3.0 * Ln[AL_X + 1];
@@ -371,7 +526,18 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
             const unsigned long long bal = __ballot(hit);
             if (hit) {
                 const int pos = n + __popcll(bal & ((1ull << tid) - 1ull));
-                if (pos < kMaxNeighbours) s_nb[pos] = q;
+                if (pos < kMaxNeighbours) {
+                    const PartDev& Q = a.s.parts[q];
+                    s_nb[pos] = q;
+                    NbBox& B = s_box[pos];
+                    B.fx0 = Q.bx0;
+                    B.fy0 = Q.by0;
+                    B.fw = Q.bw > 0 ? Q.bw : 0;
+                    B.fh = Q.bh;
+                    B.foff = Q.patch_off;
+                    B.ax0 = B.ay0 = B.aw = B.ah = 0;
+                    B.aoff = 0;
+                }
             }
             n += __popcll(bal);
         }
@@ -383,21 +549,19 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
     }
     const int ncell = aw * ah;
     double* apatch = a.apatch + A->aoff * kAdjCell;
-    for (int q = tid; q < ncell * kAdjCell; q += blockDim.x) apatch[q] = 0.0;
-    {
-        StepArgs sa = a.s;
-        sa.tlist = a.atlist;
-        mark_tiles(sa, c, ax0u, ay0u, aw, ah, tid, blockDim.x);
-    }
+    for (int q = tid; q < min(ncell, kAdjMaskCells); q += blockDim.x) s_mask[q] = 0ull;
     __syncthreads();
     const int nnb = s_nnb;
     const double lFx = s_lF[0], lFy = s_lF[1], lM = s_lF[2];
 
     const int lo = tid / 9, k = tid % 9;
-    for (int r0 = 0; r0 < nm; r0 += kRound) {
+    for (int r0 = 0; r0 < nm; r0 += kAdjRound) {
         const int l = r0 + lo;
-        if (l < nm) {
-            const double2 x = a.s.xi[mb + l], nb = a.s.nrm[mb + l];
+        const bool act = lo < kAdjRound && l < nm;
+        const bool lead = tid < kAdjRound && r0 + tid < nm;
+        // (1) one probe-stencil node per thread: weight and level-n fields
+        if (act) {
+            const double2 x = r0 == 0 ? pre_x : a.s.xi[mb + l], nb = r0 == 0 ? pre_n : a.s.nrm[mb + l];
             const double rx = cs * x.x - sn * x.y, ry = sn * x.x + cs * x.y;
             const double nxl = cs * nb.x - sn * nb.y, nyl = sn * nb.x + cs * nb.y;
             const double xp = X0 + rx + dn * nxl, yp = X1 + ry + dn * nyl;
@@ -410,7 +574,12 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
                 double f[9], jx, jy, fx, fy;
                 pull_node_f64<ST>(a.s.fin, c, ni, nj, f);
                 moments_f64(f, c, rho, jx, jy);
-                fwd_force(a, c, s_nb, nnb, ni, nj, fx, fy);
+                if (nnb <= kMaxNeighbours) {
+                    double t[kAdjCell];
+                    patch_terms_lds<0>(a, c, s_box, nnb, ni, nj, fx, fy, t);
+                } else {
+                    fwd_force(a, c, s_nb, nnb, ni, nj, fx, fy);
+                }
                 ux = (jx + 0.5 * fx) / rho;
                 uy = (jy + 0.5 * fy) / rho;
             }
@@ -418,35 +587,55 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
             s_r[tid] = rho;
             s_ux[tid] = ux;
             s_uy[tid] = uy;
-            if (k == 0) s_anc[lo] = make_int2(i0, j0);
+            if (k == 0) {
+                s_anc[lo] = make_int2(i0, j0);
+                if (ncell <= kAdjMaskCells) atomicOr(&s_mask[(j0 - ay0u) * aw + (i0 - ax0u)], 1ull << lo);
+                s_xp[lo][0] = xp;
+                s_xp[lo][1] = yp;
+                s_geo[lo][0] = rx;
+                s_geo[lo][1] = ry;
+                s_geo[lo][2] = nxl;
+                s_geo[lo][3] = nyl;
+            } else if (k == 1) {
+                const double* gk = a.gmk + (long long)(mb + l) * 5;
+                for (int e = 0; e < 5; ++e) s_g[lo][e] = gk[e];
+            }
         }
         __syncthreads();
-        if (tid < kRound && r0 + tid < nm) {
-            const int lm = tid, l = r0 + lm;
-            const double2 x = a.s.xi[mb + l], nb = a.s.nrm[mb + l];
-            const double rx = cs * x.x - sn * x.y, ry = sn * x.x + cs * x.y;
-            const double nxl = cs * nb.x - sn * nb.y, nyl = sn * nb.x + cs * nb.y;
-            const double xp = X0 + rx + dn * nxl, yp = X1 + ry + dn * nyl;
+        // (2) per marker: MLS inverse, the forward traction, and the
+        // transpose of t -> F, M down to the probe field derivatives
+        double rx = 0.0, ry = 0.0, nxl = 0.0, nyl = 0.0, lrx = 0.0, lry = 0.0, lnx = 0.0, lny = 0.0;
+        double c_alp = 0.0, c_om = 0.0, lalx = 0.0, laly = 0.0;
+        if (lead) {
+            const int lm = tid, lg = r0 + lm;
+            rx = s_geo[lm][0];
+            ry = s_geo[lm][1];
+            nxl = s_geo[lm][2];
+            nyl = s_geo[lm][3];
+            const double xp = s_xp[lm][0], yp = s_xp[lm][1];
             const int i0 = s_anc[lm].x, j0 = s_anc[lm].y;
             const double* w = s_w + lm * 9;
-            const MlsInv iv = mls_inverse(c, w, i0, j0, xp, yp, true);
-            double phi[9], dpx[9], dpy[9];
+            const MlsInv iv = mls_inverse_adj(c, w, i0, j0, xp, yp);
+            s_B[lm][0] = iv.i00;
+            s_B[lm][1] = iv.i01;
+            s_B[lm][2] = iv.i02;
+            s_B[lm][3] = iv.i11;
+            s_B[lm][4] = iv.i12;
+            s_B[lm][5] = iv.i22;
             double rP = 0.0, dudx = 0.0, dudy = 0.0, dvdx = 0.0, dvdy = 0.0;
-#pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-                phi[q] = dpx[q] = dpy[q] = 0.0;
                 if (!node_valid(c, ii, jj)) continue;
                 const double ddx = (double)ii - xp, ddy = (double)jj - yp;
-                phi[q] = w[q] * (iv.i00 + iv.i01 * ddx + iv.i02 * ddy);
-                dpx[q] = w[q] * (iv.i01 + iv.i11 * ddx + iv.i12 * ddy);
-                dpy[q] = w[q] * (iv.i02 + iv.i12 * ddx + iv.i22 * ddy);
+                const double phi = w[q] * (iv.i00 + iv.i01 * ddx + iv.i02 * ddy);
+                const double dpx = w[q] * (iv.i01 + iv.i11 * ddx + iv.i12 * ddy);
+                const double dpy = w[q] * (iv.i02 + iv.i12 * ddx + iv.i22 * ddy);
                 const double rq = s_r[lm * 9 + q], uq = s_ux[lm * 9 + q], vq = s_uy[lm * 9 + q];
-                rP += phi[q] * rq;
-                dudx += dpx[q] * uq;
-                dudy += dpy[q] * uq;
-                dvdx += dpx[q] * vq;
-                dvdy += dpy[q] * vq;
+                rP += phi * rq;
+                dudx += dpx * uq;
+                dudy += dpy * uq;
+                dvdx += dpx * vq;
+                dvdy += dpy * vq;
             }
             const double pP = (rP - 1.0) / 3.0;
             const double txx = nu * (2.0 * dudx), txy = nu * (dudy + dvdx), tyy = nu * (2.0 * dvdy);
@@ -455,113 +644,158 @@ __global__ __launch_bounds__(kIbmThreads) void adj_traction_kernel(AdjArgs a) {
             const double pl = pP + dn * (alx * nxl + aly * nyl);
             const double tx = txx * nxl + txy * nyl - pl * nxl;
             const double ty = txy * nxl + tyy * nyl - pl * nyl;
-            const double S = a.s.ds[mb + l];
-            // transpose of F = sum t S, M = sum (r x t) S
+            const double S = a.s.ds[mb + lg];
+            // F = sum t S, M = sum (r x t) S
             const double ltx = S * (lFx - lM * ry), lty = S * (lFy + lM * rx);
-            double* gk = a.gmk + (long long)(mb + l) * 5;
-            gk[4] += lFx * tx + lFy * ty + lM * (rx * ty - ry * tx);
-            double lrx = S * lM * ty, lry = -S * lM * tx;
+            s_g[lm][4] += lFx * tx + lFy * ty + lM * (rx * ty - ry * tx);
+            lrx = S * lM * ty;
+            lry = -S * lM * tx;
             // t = tau n - p_l n
             const double ltxx = ltx * nxl, ltxy = ltx * nyl + lty * nxl, ltyy = lty * nyl;
             const double lpl = -(ltx * nxl + lty * nyl);
-            double lnx = ltx * (txx - pl) + lty * txy, lny = ltx * txy + lty * (tyy - pl);
+            lnx = ltx * (txx - pl) + lty * txy;
+            lny = ltx * txy + lty * (tyy - pl);
             // p_l = p_P + dn (a_l . n), a_l = acc + alp z x r - Om^2 r
-            const double lalx = dn * lpl * nxl, laly = dn * lpl * nyl;
+            lalx = dn * lpl * nxl;
+            laly = dn * lpl * nyl;
             lnx += dn * lpl * alx;
             lny += dn * lpl * aly;
-            const double c_alp = -ry * lalx + rx * laly;
-            const double c_om = -2.0 * Om * (lalx * rx + laly * ry);
+            c_alp = -ry * lalx + rx * laly;
+            c_om = -2.0 * Om * (lalx * rx + laly * ry);
             lrx += -Om * Om * lalx + alp * laly;
             lry += -alp * lalx - Om * Om * laly;
             // p_P = (rho_P - 1)/3, tau = nu (grad u + grad u^T)
-            const double lrP = lpl / 3.0;
-            const double ldudx = 2.0 * nu * ltxx, ldudy = nu * ltxy, ldvdx = nu * ltxy, ldvdy = 2.0 * nu * ltyy;
-            double lpsi[9][3];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const double rq = s_r[lm * 9 + q], uq = s_ux[lm * 9 + q], vq = s_uy[lm * 9 + q];
-                s_dep[lm * 9 + q][0] = phi[q] * lrP;
-                s_dep[lm * 9 + q][1] = dpx[q] * ldudx + dpy[q] * ldudy;
-                s_dep[lm * 9 + q][2] = dpx[q] * ldvdx + dpy[q] * ldvdy;
-                lpsi[q][0] = lrP * rq;
-                lpsi[q][1] = ldudx * uq + ldvdx * vq;
-                lpsi[q][2] = ldudy * uq + ldvdy * vq;
+            s_sc[lm][0] = lpl / 3.0;
+            s_sc[lm][1] = 2.0 * nu * ltxx;
+            s_sc[lm][2] = nu * ltxy;
+            s_sc[lm][3] = nu * ltxy;
+            s_sc[lm][4] = 2.0 * nu * ltyy;
+        }
+        __syncthreads();
+        // (3) per node: field terms for the patch and the share of S
+        double p[3] = {1.0, 0.0, 0.0}, z[3] = {0.0, 0.0, 0.0}, y[3] = {0.0, 0.0, 0.0};
+        double lp[3] = {0.0, 0.0, 0.0}, wk = 0.0;
+        if (act) {
+            const int2 an = s_anc[lo];
+            const int ii = an.x + k % 3 - 1, jj = an.y + k / 3 - 1;
+            double S9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            s_dep[tid][0] = s_dep[tid][1] = s_dep[tid][2] = 0.0;
+            if (node_valid(c, ii, jj)) {
+                const double* B6 = s_B[lo];
+                wk = s_w[tid];
+                p[1] = (double)ii - s_xp[lo][0];
+                p[2] = (double)jj - s_xp[lo][1];
+                const double phi = wk * (B6[0] + B6[1] * p[1] + B6[2] * p[2]);
+                const double dpx = wk * (B6[1] + B6[3] * p[1] + B6[4] * p[2]);
+                const double dpy = wk * (B6[2] + B6[4] * p[1] + B6[5] * p[2]);
+                const double lrP = s_sc[lo][0], ldudx = s_sc[lo][1], ldudy = s_sc[lo][2];
+                const double ldvdx = s_sc[lo][3], ldvdy = s_sc[lo][4];
+                s_dep[tid][0] = phi * lrP;
+                s_dep[tid][1] = dpx * ldudx + dpy * ldudy;
+                s_dep[tid][2] = dpx * ldvdx + dpy * ldvdy;
+                const double rq = s_r[tid], uq = s_ux[tid], vq = s_uy[tid];
+                lp[0] = lrP * rq;
+                lp[1] = ldudx * uq + ldvdx * vq;
+                lp[2] = ldudy * uq + ldvdy * vq;
+                mls_share(B6, p, lp, wk, z, y, S9);
             }
-            double lxp, lyp;
-            mls_point_adj(c, w, iv, i0, j0, xp, yp, lpsi, lxp, lyp);
+#pragma unroll
+            for (int e = 0; e < 9; ++e) s_S[tid][e] = S9[e];
+        }
+        __syncthreads();
+        // (4) S of each marker (thread (marker, entry)); deposit the field terms
+        if (act) {
+            double Se = 0.0;
+            for (int q = 0; q < 9; ++q) Se += s_S[lo * 9 + q][k];
+            s_Sm[lo][k] = Se;
+        }
+        deposit_round<3, 0, 3, 3>(apatch, ax0u, ay0u, aw, ah, ncell, s_anc, s_mask, s_dep, min(kAdjRound, nm - r0), r0 == 0);
+        __syncthreads();
+        // (5) per node: its term of the derivative with respect to the probe
+        if (act) {
+            double ox = 0.0, oy = 0.0;
+            if (wk != 0.0) mls_term(c, s_Sm[lo], p, z, y, lp, wk, ox, oy);
+            s_S[tid][0] = ox;
+            s_S[tid][1] = oy;
+        }
+        __syncthreads();
+        // (6) per marker: probe position = X + r + dn n, r = R(th) xi, n = R(th) nu
+        if (lead) {
+            const int lm = tid, lg = r0 + lm;
+            double lxp = 0.0, lyp = 0.0;
+            for (int q = 0; q < 9; ++q) {
+                lxp += s_S[lm * 9 + q][0];
+                lyp += s_S[lm * 9 + q][1];
+            }
             lrx += lxp;
             lry += lyp;
             lnx += dn * lxp;
             lny += dn * lyp;
-            // n = R(th) nu, r = R(th) xi
-            gk[2] += cs * lnx + sn * lny;
-            gk[3] += -sn * lnx + cs * lny;
-            gk[0] += cs * lrx + sn * lry;
-            gk[1] += -sn * lrx + cs * lry;
-            const double c_th = -nyl * lnx + nxl * lny - ry * lrx + rx * lry;
-            double* ps = a.pscr + (long long)(mb + l) * 8;
-            ps[0] = lxp;
-            ps[1] = lyp;
-            ps[2] = c_th;
-            ps[3] = c_om;
-            ps[4] = lalx;
-            ps[5] = laly;
-            ps[6] = c_alp;
+            double* gk = a.gmk + (long long)(mb + lg) * 5;
+            gk[0] = s_g[lm][0] + (cs * lrx + sn * lry);
+            gk[1] = s_g[lm][1] + (-sn * lrx + cs * lry);
+            gk[2] = s_g[lm][2] + (cs * lnx + sn * lny);
+            gk[3] = s_g[lm][3] + (-sn * lnx + cs * lny);
+            gk[4] = s_g[lm][4];
+            s_pt[lm][0] = lxp;
+            s_pt[lm][1] = lyp;
+            s_pt[lm][2] = -nyl * lnx + nxl * lny - ry * lrx + rx * lry;
+            s_pt[lm][3] = c_om;
+            s_pt[lm][4] = lalx;
+            s_pt[lm][5] = laly;
+            s_pt[lm][6] = c_alp;
         }
         __syncthreads();
-        // deposit the round's field terms, each cell summing its markers in
-        // ascending order (the cell's thread is the same in every round)
-        const int nr = min(kRound, nm - r0);
-        for (int q = tid; q < ncell; q += blockDim.x) {
-            const int cx = ax0u + q % aw, cy = ay0u + q / aw;
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-            for (int m = 0; m < nr; ++m) {
-                const int2 an = s_anc[m];
-                const int ddx = cx - an.x, ddy = cy - an.y;
-                if (ddx < -1 || ddx > 1 || ddy < -1 || ddy > 1) continue;
-                const int kk = 3 * (ddy + 1) + (ddx + 1);
-                t0 += s_dep[m * 9 + kk][0];
-                t1 += s_dep[m * 9 + kk][1];
-                t2 += s_dep[m * 9 + kk][2];
-            }
-            double* v = apatch + (long long)q * kAdjCell;
-            v[0] += t0;
-            v[1] += t1;
-            v[2] += t2;
+        // clear the round's anchor bits; running per-particle sums over the
+        // markers, ascending
+        if (act && k == 0 && ncell <= kAdjMaskCells) s_mask[(s_anc[lo].y - ay0u) * aw + (s_anc[lo].x - ax0u)] = 0ull;
+        if (tid < 7) {
+            const int nr = min(kAdjRound, nm - r0);
+            double acc = s_run[tid];
+            for (int m = 0; m < nr; ++m) acc += s_pt[m][tid];
+            s_run[tid] = acc;
         }
         __syncthreads();
     }
-    // per-particle sums over the markers, ascending
-    if (tid < 7) {
-        double s = 0.0;
-        for (int l = 0; l < nm; ++l) s += a.pscr[(long long)(mb + l) * 8 + tid];
-        s_sum[tid] = s;
-    }
-    __syncthreads();
     if (tid == 0) {
         double* L = A->l;
         for (int j = 0; j < AL_N; ++j) L[j] = s_part[j];
-        L[AL_X] += s_sum[0];
-        L[AL_X + 1] += s_sum[1];
-        L[AL_TH] += s_sum[2];
-        L[AL_OM] += s_sum[3];
-        L[AL_ACC] += s_sum[4];
-        L[AL_ACC + 1] += s_sum[5];
-        L[AL_ALP] += s_sum[6];
+        L[AL_X] += s_run[0];
+        L[AL_X + 1] += s_run[1];
+        L[AL_TH] += s_run[2];
+        L[AL_OM] += s_run[3];
+        L[AL_ACC] += s_run[4];
+        L[AL_ACC + 1] += s_run[5];
+        L[AL_ALP] += s_run[6];
     }
+    // list the tiles the adjoint patch touches for the lattice pass (its
+    // latency overlaps the end of the kernel)
+    StepArgs sa = a.s;
+    sa.tlist = a.atlist;
+    mark_tiles(sa, c, ax0u, ay0u, aw, ah, tid, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
 // Kernel B: adjoint of the immersed-boundary force and spreading.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(kIbmThreads) void adj_ibm_kernel(AdjArgs a) {
-    __shared__ double s_w[kIbmThreads], s_usx[kIbmThreads], s_usy[kIbmThreads];
-    __shared__ double s_lfx[kIbmThreads], s_lfy[kIbmThreads];
-    __shared__ double s_dep[kIbmThreads][2];
-    __shared__ int2 s_anc[kRound];
-    __shared__ double s_sum[8];
+__global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
+    __shared__ double s_w[kAdjThreads], s_usx[kAdjThreads], s_usy[kAdjThreads];
+    __shared__ double s_lfx[kAdjThreads], s_lfy[kAdjThreads];
+    __shared__ double s_dep[kAdjThreads][2];
+    __shared__ double s_S[kAdjThreads][9];
+    __shared__ double s_Sm[kAdjRound][9];
+    __shared__ double s_B[kAdjRound][6];
+    __shared__ double s_sc[kAdjRound][5];      // F (2), d/d U (2), c_l
+    __shared__ double s_xp[kAdjRound][2];
+    __shared__ double s_geo[kAdjRound][2];     // r of the marker
+    __shared__ double s_g[kAdjRound][5];       // its accumulated shape gradients
+    __shared__ double s_pt[kAdjRound][8];      // its particle terms
+    __shared__ int2 s_anc[kAdjRound];
+    __shared__ double s_run[8];
     __shared__ int s_nb[kMaxNeighbours];
+    __shared__ NbBox s_box[kMaxNeighbours];
+    __shared__ unsigned long long s_mask[kAdjMaskCells];
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     if (b >= a.s.nparts) return;
@@ -571,21 +805,58 @@ __global__ __launch_bounds__(kIbmThreads) void adj_ibm_kernel(AdjArgs a) {
     if (A->aw <= 0) return;
     const int nm = P->nm, mb = P->mbeg;
     const double X0 = P->X[0], X1 = P->X[1], th = P->th;
-    const double Om = P->Om;
+    const double Om = P->Om, V0 = P->V[0], V1 = P->V[1];
     const double cs = cos(th), sn = sin(th);
     const int nnb = A->nnb;
-    if (tid < kMaxNeighbours) s_nb[tid] = A->nb[tid];
+    // marker geometry of the first round, requested early
+    double2 pre_x = make_double2(0.0, 0.0);
+    if (tid / 9 < kAdjRound && tid / 9 < nm) pre_x = a.s.xi[mb + tid / 9];
+    if (tid < kMaxNeighbours) {
+        s_nb[tid] = A->nb[tid];
+        if (tid < nnb) {
+            const int q = A->nb[tid];
+            const PartDev& Q = a.s.parts[q];
+            const AdjPart& QA = a.ap[q];
+            NbBox& B = s_box[tid];
+            B.fx0 = Q.bx0;
+            B.fy0 = Q.by0;
+            B.fw = Q.bw > 0 ? Q.bw : 0;
+            B.fh = Q.bh;
+            B.foff = Q.patch_off;
+            B.ax0 = QA.ax0;
+            B.ay0 = QA.ay0;
+            B.aw = QA.aw;
+            B.ah = QA.ah;
+            B.aoff = QA.aoff;
+        }
+    }
+    if (tid < 8) s_run[tid] = 0.0;
     int ax0u, ay0u, aw, ah;
     stencil_box(X0, X1, P->rb + c.dn, ax0u, ay0u, aw, ah);
     const int ncell = aw * ah;
     double* apatch = a.apatch + A->aoff * kAdjCell;
+    for (int q = tid; q < min(ncell, kAdjMaskCells); q += blockDim.x) s_mask[q] = 0ull;
     __syncthreads();
 
     const int lo = tid / 9, k = tid % 9;
-    for (int r0 = 0; r0 < nm; r0 += kRound) {
+    for (int r0 = 0; r0 < nm; r0 += kAdjRound) {
         const int l = r0 + lo;
-        if (l < nm) {
-            const Marker m = marker_at(a.s, mb + l, X0, X1, cs, sn);
+        const bool act = lo < kAdjRound && l < nm;
+        const bool lead = tid < kAdjRound && r0 + tid < nm;
+        // (1) one marker-stencil node per thread: u*, and d/d f_lb from the
+        // transpose of the collision there (probe terms included)
+        if (act) {
+            Marker m;
+            if (r0 == 0) {
+                m.rx = cs * pre_x.x - sn * pre_x.y;
+                m.ry = sn * pre_x.x + cs * pre_x.y;
+                m.xl = X0 + m.rx;
+                m.yl = X1 + m.ry;
+                m.i0 = (int)floor(m.xl + 0.5);
+                m.j0 = (int)floor(m.yl + 0.5);
+            } else {
+                m = marker_at(a.s, mb + l, X0, X1, cs, sn);
+            }
             double dx, dy;
             int ni, nj;
             double w = 0.0, usx = 0.0, usy = 0.0, lfx = 0.0, lfy = 0.0;
@@ -597,7 +868,8 @@ __global__ __launch_bounds__(kIbmThreads) void adj_ibm_kernel(AdjArgs a) {
                 usx = jx / rho;
                 usy = jy / rho;
                 // probe terms only: the marker terms are being written
-                patch_terms<3>(a, c, s_nb, nnb, ni, nj, fx, fy, t);
+                if (nnb <= kMaxNeighbours) patch_terms_lds<3>(a, c, s_box, nnb, ni, nj, fx, fy, t);
+                else patch_terms<3>(a, c, s_nb, nnb, ni, nj, fx, fy, t);
                 const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) lfc[i] = lam_push<ST>(a.lam_in, c, i, ni, nj);
@@ -611,92 +883,144 @@ __global__ __launch_bounds__(kIbmThreads) void adj_ibm_kernel(AdjArgs a) {
             s_usy[tid] = usy;
             s_lfx[tid] = lfx;
             s_lfy[tid] = lfy;
-            if (k == 0) s_anc[lo] = make_int2(m.i0, m.j0);
+            if (k == 0) {
+                s_anc[lo] = make_int2(m.i0, m.j0);
+                if (ncell <= kAdjMaskCells) atomicOr(&s_mask[(m.j0 - ay0u) * aw + (m.i0 - ax0u)], 1ull << lo);
+                s_xp[lo][0] = m.xl;
+                s_xp[lo][1] = m.yl;
+                s_geo[lo][0] = m.rx;
+                s_geo[lo][1] = m.ry;
+            } else if (k == 1) {
+                const double* gk = a.gmk + (long long)(mb + l) * 5;
+                for (int e = 0; e < 5; ++e) s_g[lo][e] = gk[e];
+            }
         }
         __syncthreads();
-        if (tid < kRound && r0 + tid < nm) {
-            const int lm = tid, l = r0 + lm;
-            const Marker m = marker_at(a.s, mb + l, X0, X1, cs, sn);
-            const double cl = c.spread_unit ? 1.0 : a.s.ds[mb + l];
-            const double* w = s_w + lm * 9;
-            const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, true);
-            double phi[9];
+        // (2) per marker: MLS inverse
+        if (lead) {
+            const int lm = tid;
+            const MlsInv iv = mls_inverse_adj(c, s_w + lm * 9, s_anc[lm].x, s_anc[lm].y, s_xp[lm][0], s_xp[lm][1]);
+            s_B[lm][0] = iv.i00;
+            s_B[lm][1] = iv.i01;
+            s_B[lm][2] = iv.i02;
+            s_B[lm][3] = iv.i11;
+            s_B[lm][4] = iv.i12;
+            s_B[lm][5] = iv.i22;
+        }
+        __syncthreads();
+        // (3) per node: phi and its products
+        double p[3] = {1.0, 0.0, 0.0}, phi = 0.0, wk = 0.0;
+        if (act) {
+            const int2 an = s_anc[lo];
+            const int ii = an.x + k % 3 - 1, jj = an.y + k / 3 - 1;
+            if (node_valid(c, ii, jj)) {
+                const double* B6 = s_B[lo];
+                wk = s_w[tid];
+                p[1] = (double)ii - s_xp[lo][0];
+                p[2] = (double)jj - s_xp[lo][1];
+                phi = wk * (B6[0] + B6[1] * p[1] + B6[2] * p[2]);
+            }
+            s_S[tid][0] = phi * s_usx[tid];
+            s_S[tid][1] = phi * s_usy[tid];
+            s_S[tid][2] = phi * s_lfx[tid];
+            s_S[tid][3] = phi * s_lfy[tid];
+        }
+        __syncthreads();
+        // (4) per marker: U = sum phi u*, F = U_b - U, the adjoint of F_l
+        // from f_lb = sum c_l phi F_l, and of U
+        double lFx = 0.0, lFy = 0.0, mrx = 0.0, mry = 0.0;
+        if (lead) {
+            const int lm = tid, lg = r0 + lm;
+            mrx = s_geo[lm][0];
+            mry = s_geo[lm][1];
             double Ux = 0.0, Uy = 0.0, slx = 0.0, sly = 0.0;
-#pragma unroll
             for (int q = 0; q < 9; ++q) {
-                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                phi[q] = 0.0;
-                if (!node_valid(c, ii, jj)) continue;
-                const double ddx = (double)ii - m.xl, ddy = (double)jj - m.yl;
-                phi[q] = w[q] * (iv.i00 + iv.i01 * ddx + iv.i02 * ddy);
-                Ux += phi[q] * s_usx[lm * 9 + q];
-                Uy += phi[q] * s_usy[lm * 9 + q];
-                slx += phi[q] * s_lfx[lm * 9 + q];
-                sly += phi[q] * s_lfy[lm * 9 + q];
+                Ux += s_S[lm * 9 + q][0];
+                Uy += s_S[lm * 9 + q][1];
+                slx += s_S[lm * 9 + q][2];
+                sly += s_S[lm * 9 + q][3];
             }
-            const double ubx = P->V[0] - Om * m.ry, uby = P->V[1] + Om * m.rx;
-            const double Fx = ubx - Ux, Fy = uby - Uy;
-            // f_lb = sum_l c_l phi_l F_l, F_l = U_b - sum phi u*
-            const double lFx = cl * slx, lFy = cl * sly;
-            double* gk = a.gmk + (long long)(mb + l) * 5;
-            if (!c.spread_unit) gk[4] += Fx * slx + Fy * sly;
-            const double lUx = -lFx, lUy = -lFy;
-            double lpsi[9][3];
+            const double cl = c.spread_unit ? 1.0 : a.s.ds[mb + lg];
+            const double Fx = (V0 - Om * mry) - Ux, Fy = (V1 + Om * mrx) - Uy;
+            lFx = cl * slx;
+            lFy = cl * sly;
+            if (!c.spread_unit) s_g[lm][4] += Fx * slx + Fy * sly;
+            s_sc[lm][0] = Fx;
+            s_sc[lm][1] = Fy;
+            s_sc[lm][2] = -lFx;
+            s_sc[lm][3] = -lFy;
+            s_sc[lm][4] = cl;
+        }
+        __syncthreads();
+        // (5) per node: d/d phi_k, the u* terms for the patch, share of S
+        double z[3] = {0.0, 0.0, 0.0}, y[3] = {0.0, 0.0, 0.0}, lp[3] = {0.0, 0.0, 0.0};
+        if (act) {
+            double S9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            const double Fx = s_sc[lo][0], Fy = s_sc[lo][1], lUx = s_sc[lo][2], lUy = s_sc[lo][3];
+            s_dep[tid][0] = phi * lUx;
+            s_dep[tid][1] = phi * lUy;
+            if (wk != 0.0) {
+                lp[0] = s_sc[lo][4] * (Fx * s_lfx[tid] + Fy * s_lfy[tid]) + lUx * s_usx[tid] + lUy * s_usy[tid];
+                mls_share(s_B[lo], p, lp, wk, z, y, S9);
+            }
 #pragma unroll
+            for (int e = 0; e < 9; ++e) s_S[tid][e] = S9[e];
+        }
+        __syncthreads();
+        if (act) {
+            double Se = 0.0;
+            for (int q = 0; q < 9; ++q) Se += s_S[lo * 9 + q][k];
+            s_Sm[lo][k] = Se;
+        }
+        deposit_round<2, 3, 2, kAdjCell>(apatch, ax0u, ay0u, aw, ah, ncell, s_anc, s_mask, s_dep, min(kAdjRound, nm - r0), r0 == 0);
+        __syncthreads();
+        if (act) {
+            double ox = 0.0, oy = 0.0;
+            if (wk != 0.0) mls_term(c, s_Sm[lo], p, z, y, lp, wk, ox, oy);
+            s_S[tid][0] = ox;
+            s_S[tid][1] = oy;
+        }
+        __syncthreads();
+        // (6) per marker: x_l = X + r, U_b = V + Om z x r, r = R(th) xi
+        if (lead) {
+            const int lm = tid, lg = r0 + lm;
+            double lx = 0.0, ly = 0.0;
             for (int q = 0; q < 9; ++q) {
-                lpsi[q][0] = cl * (Fx * s_lfx[lm * 9 + q] + Fy * s_lfy[lm * 9 + q]) +
-                             lUx * s_usx[lm * 9 + q] + lUy * s_usy[lm * 9 + q];
-                lpsi[q][1] = lpsi[q][2] = 0.0;
-                s_dep[lm * 9 + q][0] = phi[q] * lUx;
-                s_dep[lm * 9 + q][1] = phi[q] * lUy;
+                lx += s_S[lm * 9 + q][0];
+                ly += s_S[lm * 9 + q][1];
             }
-            double lx, ly;
-            mls_point_adj(c, w, iv, m.i0, m.j0, m.xl, m.yl, lpsi, lx, ly);
-            // U_b = V + Om z x r, x_l = X + r, r = R(th) xi
             const double lrx = Om * lFy + lx, lry = -Om * lFx + ly;
-            gk[0] += cs * lrx + sn * lry;
-            gk[1] += -sn * lrx + cs * lry;
-            double* ps = a.pscr + (long long)(mb + l) * 8;
-            ps[0] = lx;
-            ps[1] = ly;
-            ps[2] = -m.ry * lrx + m.rx * lry;
-            ps[3] = lFx;
-            ps[4] = lFy;
-            ps[5] = -m.ry * lFx + m.rx * lFy;
+            double* gk = a.gmk + (long long)(mb + lg) * 5;
+            gk[0] = s_g[lm][0] + (cs * lrx + sn * lry);
+            gk[1] = s_g[lm][1] + (-sn * lrx + cs * lry);
+            gk[2] = s_g[lm][2];
+            gk[3] = s_g[lm][3];
+            gk[4] = s_g[lm][4];
+            s_pt[lm][0] = lx;
+            s_pt[lm][1] = ly;
+            s_pt[lm][2] = -mry * lrx + mrx * lry;
+            s_pt[lm][3] = lFx;
+            s_pt[lm][4] = lFy;
+            s_pt[lm][5] = -mry * lFx + mrx * lFy;
         }
         __syncthreads();
-        const int nr = min(kRound, nm - r0);
-        for (int q = tid; q < ncell; q += blockDim.x) {
-            const int cx = ax0u + q % aw, cy = ay0u + q / aw;
-            double t0 = 0.0, t1 = 0.0;
-            for (int mm = 0; mm < nr; ++mm) {
-                const int2 an = s_anc[mm];
-                const int ddx = cx - an.x, ddy = cy - an.y;
-                if (ddx < -1 || ddx > 1 || ddy < -1 || ddy > 1) continue;
-                const int kk = 3 * (ddy + 1) + (ddx + 1);
-                t0 += s_dep[mm * 9 + kk][0];
-                t1 += s_dep[mm * 9 + kk][1];
-            }
-            double* v = apatch + (long long)q * kAdjCell;
-            v[3] += t0;
-            v[4] += t1;
+        if (act && k == 0 && ncell <= kAdjMaskCells) s_mask[(s_anc[lo].y - ay0u) * aw + (s_anc[lo].x - ax0u)] = 0ull;
+        if (tid < 6) {
+            const int nr = min(kAdjRound, nm - r0);
+            double acc = s_run[tid];
+            for (int m = 0; m < nr; ++m) acc += s_pt[m][tid];
+            s_run[tid] = acc;
         }
         __syncthreads();
     }
-    if (tid < 6) {
-        double s = 0.0;
-        for (int l = 0; l < nm; ++l) s += a.pscr[(long long)(mb + l) * 8 + tid];
-        s_sum[tid] = s;
-    }
-    __syncthreads();
     if (tid == 0) {
         double* L = A->l;
-        L[AL_X] += s_sum[0];
-        L[AL_X + 1] += s_sum[1];
-        L[AL_TH] += s_sum[2];
-        L[AL_V] += s_sum[3];
-        L[AL_V + 1] += s_sum[4];
-        L[AL_OM] += s_sum[5];
+        L[AL_X] += s_run[0];
+        L[AL_X + 1] += s_run[1];
+        L[AL_TH] += s_run[2];
+        L[AL_V] += s_run[3];
+        L[AL_V + 1] += s_run[4];
+        L[AL_OM] += s_run[5];
     }
 }
 
@@ -718,81 +1042,84 @@ __device__ __forceinline__ long long wall_slot(const AdjArgs& a, int chan, const
     return -1;
 }
 
+// One wave per 64-node chunk of a tile (chunks = tile nodes / 64): the
+// forward tile table and its particle lists are reused, and small lattices
+// still spread over many compute units.
 template <int ST>
-__global__ __launch_bounds__(256) void adj_lattice_kernel(AdjArgs a, int tw, int npt) {
+__global__ __launch_bounds__(64) void adj_lattice_kernel(AdjArgs a, int tw, int chunks) {
     using LT = typename LamT<ST>::T;
     LT* __restrict__ lout = (LT*)a.lam_out;
-    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+    const int t = blockIdx.x / chunks, part = blockIdx.x % chunks;
+    if (t >= a.s.ntiles) return;
     const int* tl_cur = a.atlist + (long long)a.s.parity * a.s.ntiles * kTileList;
     int* tl_next = a.atlist + (long long)(1 - a.s.parity) * a.s.ntiles * kTileList;
-    for (int t = blockIdx.x; t < a.s.ntiles; t += gridDim.x) {
-        const TileDev* tp = a.s.tiles + t;
-        const int tx0 = uni(tp->x0), ty0 = uni(tp->y0), ch = uni(tp->chan);
-        const ChanDev c = load_chan(a.s.chan + ch);
-        const int* e = tl_cur + (long long)t * kTileList;
-        const int cnt = uni(e[0]);
-        if (threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
-        int list[kMaxNeighbours];
-        int nlist = 0;
-        if (cnt > kTileList - 1) {
-            nlist = kMaxNeighbours + 1;  // overflow: scan the channel's particles
-        } else {
-            for (int j = 0; j < cnt; ++j) {
-                const int v = uni(e[1 + j]);
-                bool dup = false;
-                for (int m = 0; m < nlist; ++m) dup |= list[m] == v;
-                if (dup) continue;
-                int k = nlist;
-                while (k > 0 && list[k - 1] > v) {
-                    list[k] = list[k - 1];
-                    --k;
-                }
-                list[k] = v;
-                ++nlist;
+    const TileDev* tp = a.s.tiles + t;
+    const int tx0 = uni(tp->x0), ty0 = uni(tp->y0), ch = uni(tp->chan);
+    const ChanDev c = load_chan(a.s.chan + ch);
+    const int* e = tl_cur + (long long)t * kTileList;
+    const int cnt = uni(e[0]);
+    int list[kMaxNeighbours];
+    int nlist = 0;
+    if (cnt > kTileList - 1) {
+        nlist = kMaxNeighbours + 1;  // overflow: scan the channel's particles
+    } else {
+        for (int j = 0; j < cnt; ++j) {
+            const int v = uni(e[1 + j]);
+            bool dup = false;
+            for (int m = 0; m < nlist; ++m) dup |= list[m] == v;
+            if (dup) continue;
+            int k = nlist;
+            while (k > 0 && list[k - 1] > v) {
+                list[k] = list[k - 1];
+                --k;
             }
-        }
-        const int x = tx0 + lx;
-        for (int r = 0; r < npt; ++r) {
-            const int y = ty0 + ly * npt + r;
-            if (x >= c.nx || y >= c.ny) continue;
-            double fr[9], f[9];
-            pull_raw_f64<ST>(a.s.fin, c, x, y, fr);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f[i] = fr[i];
-            walls_f64(c, x, y, f);
-            double rho, jx, jy;
-            moments_f64(f, c, rho, jx, jy);
-            double fx = 0.0, fy = 0.0, tt[kAdjCell] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (nlist > 0) patch_terms<kAdjCell>(a, c, list, nlist, x, y, fx, fy, tt);
-            const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho;
-            const double usx = jx / rho, usy = jy / rho;
-            double L[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) L[i] = lam_push<ST>(a.lam_in, c, i, x, y);
-            const CollAdj ca = collide_adj(L, rho, ux, uy, c.g[0] + fx, c.g[1] + fy, c.tau);
-            // u = (j + f_lb/2)/rho, u* = j/rho, rho = sum f, j = sum f e + g/2
-            const double lux = ca.lux + tt[1], luy = ca.luy + tt[2];
-            const double ljx = (lux + tt[3]) / rho, ljy = (luy + tt[4]) / rho;
-            const double lrho = ca.lrho + tt[0] - (lux * ux + luy * uy) / rho - (tt[3] * usx + tt[4] * usy) / rho;
-            const double keep = 1.0 - 1.0 / c.tau;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) L[i] = keep * L[i] + lrho + ljx * (double)ex(i) + ljy * (double)ey(i);
-            int side = -1;
-            const long long ws = wall_slot(a, ch, c, x, y, side);
-            if (ws >= 0) {
-                double gux = 0.0, guy = 0.0;
-                // wall velocity by branches: a runtime index into the channel
-                // descriptor would move it to scratch memory
-                const double uwx = side == 0 ? c.uw[0][0] : (side == 1 ? c.uw[1][0] : (side == 2 ? c.uw[2][0] : c.uw[3][0]));
-                const double uwy = side == 0 ? c.uw[0][1] : (side == 1 ? c.uw[1][1] : (side == 2 ? c.uw[2][1] : c.uw[3][1]));
-                zouhe_adj(side, fr, L, uwx, uwy, c.g[0], c.g[1], gux, guy);
-                a.gwall[ws] += gux;
-                a.gwall[ws + 1] += guy;
-            }
-#pragma unroll
-            for (int i = 0; i < 9; ++i) lout[pidx(c, i, y, x)] = (LT)L[i];
+            list[k] = v;
+            ++nlist;
         }
     }
+    const int node = part * 64 + (int)threadIdx.x;
+    const int x = tx0 + node % tw, y = ty0 + node / tw;
+    if (x < c.nx && y < c.ny) {
+        double fr[9], f[9];
+        pull_raw_f64<ST>(a.s.fin, c, x, y, fr);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = fr[i];
+        walls_f64(c, x, y, f);
+        double rho, jx, jy;
+        moments_f64(f, c, rho, jx, jy);
+        double fx = 0.0, fy = 0.0, tt[kAdjCell] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (nlist > 0) patch_terms<kAdjCell>(a, c, list, nlist, x, y, fx, fy, tt);
+        const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho;
+        const double usx = jx / rho, usy = jy / rho;
+        double L[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i] = lam_push<ST>(a.lam_in, c, i, x, y);
+        const CollAdj ca = collide_adj(L, rho, ux, uy, c.g[0] + fx, c.g[1] + fy, c.tau);
+        // u = (j + f_lb/2)/rho, u* = j/rho, rho = sum f, j = sum f e + g/2
+        const double lux = ca.lux + tt[1], luy = ca.luy + tt[2];
+        const double ljx = (lux + tt[3]) / rho, ljy = (luy + tt[4]) / rho;
+        const double lrho = ca.lrho + tt[0] - (lux * ux + luy * uy) / rho - (tt[3] * usx + tt[4] * usy) / rho;
+        const double keep = 1.0 - 1.0 / c.tau;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i] = keep * L[i] + lrho + ljx * (double)ex(i) + ljy * (double)ey(i);
+        int side = -1;
+        const long long ws = wall_slot(a, ch, c, x, y, side);
+        if (ws >= 0) {
+            double gux = 0.0, guy = 0.0;
+            // wall velocity by branches: a runtime index into the channel
+            // descriptor would move it to scratch memory
+            const double uwx = side == 0 ? c.uw[0][0] : (side == 1 ? c.uw[1][0] : (side == 2 ? c.uw[2][0] : c.uw[3][0]));
+            const double uwy = side == 0 ? c.uw[0][1] : (side == 1 ? c.uw[1][1] : (side == 2 ? c.uw[2][1] : c.uw[3][1]));
+            zouhe_adj(side, fr, L, uwx, uwy, c.g[0], c.g[1], gux, guy);
+            a.gwall[ws] += gux;
+            a.gwall[ws + 1] += guy;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lout[pidx(c, i, y, x)] = (LT)L[i];
+    }
+    // reset the other parity's list (read by no kernel of this step) for the
+    // next reverse step
+    if (part == 0 && threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -879,7 +1206,7 @@ __global__ void adj_field_kernel(AdjArgs a, int chan, double* out) {
 
 hipError_t launch_adj_traction(int store, const AdjArgs& a, hipStream_t s) {
     if (a.s.nparts <= 0) return hipSuccess;
-#define L_(ST) adj_traction_kernel<ST><<<a.s.nparts, kIbmThreads, 0, s>>>(a)
+#define L_(ST) adj_traction_kernel<ST><<<a.s.nparts, kAdjThreads, 0, s>>>(a)
     ADJ_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();
@@ -887,16 +1214,18 @@ hipError_t launch_adj_traction(int store, const AdjArgs& a, hipStream_t s) {
 
 hipError_t launch_adj_ibm(int store, const AdjArgs& a, hipStream_t s) {
     if (a.s.nparts <= 0) return hipSuccess;
-#define L_(ST) adj_ibm_kernel<ST><<<a.s.nparts, kIbmThreads, 0, s>>>(a)
+#define L_(ST) adj_ibm_kernel<ST><<<a.s.nparts, kAdjThreads, 0, s>>>(a)
     ADJ_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();
 }
 
 hipError_t launch_adj_lattice(int store, const AdjArgs& a, int tile_w, int npt, hipStream_t s) {
-    const int grid = a.s.ntiles;
+    const int chunks = 4 * npt;  // tiles hold 256 * npt nodes
+    const long long grid = (long long)a.s.ntiles * chunks;
     if (grid <= 0) return hipSuccess;
-#define L_(ST) adj_lattice_kernel<ST><<<grid, 256, 0, s>>>(a, tile_w, npt)
+    if (grid > INT_MAX) return hipErrorInvalidValue;
+#define L_(ST) adj_lattice_kernel<ST><<<(int)grid, 64, 0, s>>>(a, tile_w, chunks)
     ADJ_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();

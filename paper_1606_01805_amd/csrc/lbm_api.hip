@@ -94,7 +94,6 @@ struct lbm_handle {
     AdjPart* dap = nullptr;
     double* dapatch = nullptr;
     double* dgmk = nullptr;
-    double* dpscr = nullptr;
     double* dgwall = nullptr;
     long long* dgwoff = nullptr;
     int* datlist = nullptr;
@@ -756,7 +755,7 @@ static void free_adjoint(lbm_handle* h) {
     for (void* p : h->tape_f)
         if (p) (void)hipFree(p);
     h->tape_f.clear();
-    void* ptrs[] = {h->tape_p, h->tape_patch, h->lam[0], h->dap, h->dapatch, h->dgmk, h->dpscr,
+    void* ptrs[] = {h->tape_p, h->tape_patch, h->lam[0], h->dap, h->dapatch, h->dgmk,
                     h->dgwall, h->dgwoff, h->datlist, h->dgout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -765,7 +764,7 @@ static void free_adjoint(lbm_handle* h) {
     h->lam[0] = h->lam[1] = nullptr;
     h->dap = nullptr;
     h->dapatch = nullptr;
-    h->dgmk = h->dpscr = h->dgwall = h->dgout = nullptr;
+    h->dgmk = h->dgwall = h->dgout = nullptr;
     h->dgwoff = nullptr;
     h->datlist = nullptr;
     h->adj_seg = 0;
@@ -779,7 +778,6 @@ static AdjArgs adj_args(lbm_handle* h) {
     a.ap = h->dap;
     a.apatch = h->dapatch;
     a.gmk = h->dgmk;
-    a.pscr = h->dpscr;
     a.gwall = h->dgwall;
     a.gw_off = h->dgwoff;
     a.atlist = h->datlist;
@@ -852,7 +850,7 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
               alloc((void**)&h->tape_patch, sizeof(double2) * (size_t)max_segment * std::max<long long>(h->cells, 1)) &&
               alloc(&h->lam[0], 2 * h->lam_bytes) && alloc((void**)&h->dap, sizeof(AdjPart) * ap.size()) &&
               alloc((void**)&h->dapatch, sizeof(double) * kAdjCell * std::max<long long>(acells, 1)) &&
-              alloc((void**)&h->dgmk, sizeof(double) * 5 * nmk) && alloc((void**)&h->dpscr, sizeof(double) * 8 * nmk) &&
+              alloc((void**)&h->dgmk, sizeof(double) * 5 * nmk) &&
               alloc((void**)&h->dgwall, sizeof(double) * std::max<size_t>(gw, 1)) &&
               alloc((void**)&h->dgwoff, sizeof(long long) * nch) &&
               alloc((void**)&h->datlist, sizeof(int) * 2 * nt * kTileList) && alloc((void**)&h->dgout, sizeof(double) * 8 * nch);
@@ -897,10 +895,8 @@ extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
         a.fin = t == 0 ? h->buf[h->cur] : h->tape_f[t - 1];
         a.fout = h->tape_f[t];
         a.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
+        a.snap = h->tape_p + (size_t)t * np;  // particle snapshot after the force stage
         HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-        if (np)
-            HIPCHK(h, hipMemcpyAsync(h->tape_p + (size_t)t * np, h->dparts, sizeof(PartDev) * np,
-                                     hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
         HIPCHK(h, launch_traction(h->store, a, h->stream));
     }

@@ -78,6 +78,7 @@ struct StepArgs {
     int* tlist;              // [2][ntiles][kTileList] particles whose patches touch a tile
     int parity;              // which half of tlist this step fills / reads
     int tile_w, tile_h;      // tile extent in nodes
+    PartDev* snap;           // optional: copy of each particle after the force stage
 };
 
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
@@ -122,7 +123,6 @@ struct AdjArgs {
     AdjPart* ap;
     double* apatch;          // [cells][kAdjCell]
     double* gmk;             // [markers][5]: d xi (2), d nrm (2), d ds
-    double* pscr;            // [markers][8] per-marker particle terms
     double* gwall;           // per wall node (2 doubles), then per row (1 double)
     const long long* gw_off; // per channel: first wall accumulator
     int* atlist;             // [2][ntiles][kTileList] particles whose adjoint patches touch a tile

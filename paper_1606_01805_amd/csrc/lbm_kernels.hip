@@ -59,6 +59,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
             P->bh = 0;
             a.flags[0] = 1;
             atomicMin(&a.flags[1], (int)(*a.dstep - 1));
+            if (a.snap) a.snap[blockIdx.x] = *P;
         }
         return;
     }
@@ -71,6 +72,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
             atomicOr(&a.flags[2], 1);
             P->bw = 0;
             P->bh = 0;
+            if (a.snap) a.snap[blockIdx.x] = *P;
         }
         return;
     }
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         P->by0 = wrapc(by0u, c.ny, c.bcy == 0);
         P->bw = bw;
         P->bh = bh;
+        if (a.snap) a.snap[blockIdx.x] = *P;
     }
     const double cs = cos(th), sn = sin(th);
 
