@@ -94,7 +94,7 @@ def kernel_source_sha():
     import hashlib
 
     h = hashlib.sha1()
-    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+    for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1606_01805_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 

@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
     if (b >= a.s.nparts) return;
     const PartDev* P = a.s.parts + b;
     AdjPart* A = a.ap + b;
-    const ChanDev& c = a.s.chan[P->chan];
+    const ChanDev c = load_chan(a.s.chan + P->chan);  // in registers: not re-read after each barrier
     const int nm = P->nm, mb = P->mbeg;
     // marker geometry of the first round, requested before anything else
     double2 pre_x = make_double2(0.0, 0.0), pre_n = make_double2(0.0, 0.0);
@@ -801,7 +801,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
     if (b >= a.s.nparts) return;
     const PartDev* P = a.s.parts + b;
     AdjPart* A = a.ap + b;
-    const ChanDev& c = a.s.chan[P->chan];
+    const ChanDev c = load_chan(a.s.chan + P->chan);  // in registers: not re-read after each barrier
     if (A->aw <= 0) return;
     const int nm = P->nm, mb = P->mbeg;
     const double X0 = P->X[0], X1 = P->X[1], th = P->th;

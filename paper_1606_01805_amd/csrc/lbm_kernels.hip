@@ -21,6 +21,8 @@
 // same inputs its lattice arithmetic is the same IEEE operation sequence.
 // The FP32 and FP16S forms keep the deviation d_i = f_i - w_i and compute in
 // FP32.  The immersed-boundary and rigid-body stages are FP64 in every form.
+#include <algorithm>
+
 #include "lbm_device.h"
 
 namespace lbmk {
@@ -662,8 +664,14 @@ hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx,
     return hipGetLastError();
 }
 
+// Static LDS of the force kernel, as compiled (the mask store takes the rest).
 size_t ibm_static_lds_bytes() {
-    return 3 * sizeof(double) * kIbmThreads + sizeof(double2) * kIbmThreads + sizeof(int2) * kRound + 64;
+    size_t m = 3 * sizeof(double) * kIbmThreads + sizeof(double2) * kIbmThreads + sizeof(int2) * kRound + 64;
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, (const void*)ibm_force_kernel<ST_F64>) == hipSuccess) m = std::max(m, fa.sharedSizeBytes);
+    if (hipFuncGetAttributes(&fa, (const void*)ibm_force_kernel<ST_F32>) == hipSuccess) m = std::max(m, fa.sharedSizeBytes);
+    if (hipFuncGetAttributes(&fa, (const void*)ibm_force_kernel<ST_F16S>) == hipSuccess) m = std::max(m, fa.sharedSizeBytes);
+    return m;
 }
 
 hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s) {
