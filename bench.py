@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -63,7 +65,9 @@ def default_steps(name):
 
 def cpu_baseline(wl, seconds):
     """The FP64 oracle as it stands, one host thread, on the first channel of
-    the workload for as many steps as fit in about `seconds`."""
+    the workload for as many steps as fit in about `seconds`.  Its trajectory
+    then serves as the reference for the trajectory error of the reduced
+    storage forms, run on the GPU for the same steps from the same state."""
     import oracle
 
     cfg, parts = wl.channels[0]
@@ -73,15 +77,45 @@ def cpu_baseline(wl, seconds):
         o.add_particle(p)
     nodes = cfg["nx"] * cfg["ny"]
     t0 = time.perf_counter()
-    o.step(2, record=False)
+    first = o.step(2, record=True)
     per = (time.perf_counter() - t0) / 2
     n = max(2, int(seconds / max(per, 1e-9)))
     t0 = time.perf_counter()
-    o.step(n, record=False)
+    rest = o.step(n, record=True)
     dt = time.perf_counter() - t0
-    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n} steps of channel 0 ({cfg['nx']}x{cfg['ny']}, {len(parts)} particle(s)) "
-                      f"in FP64 on one host thread, {dt:.1f} s"}
+    out = {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "sample": f"{n} steps of channel 0 ({cfg['nx']}x{cfg['ny']}, {len(parts)} particle(s)) "
+                     f"in FP64 on one host thread, {dt:.1f} s"}
+    if parts:
+        ref = np.concatenate([first, rest], 0)
+        out["trajectory_error"] = trajectory_errors(cfg, parts, ref)
+    return out
+
+
+def trajectory_errors(cfg, parts, ref):
+    """Largest deviation from the oracle trajectory ref [n, particles, 10]
+    over the run, per storage form: positions over the wall gap (or the
+    channel height), angle in radians, angular velocity over the wall shear
+    rate (or over the largest |omega| of the reference when the walls are at
+    rest)."""
+    import torch
+
+    from paper_1606_01805_amd import Solver
+
+    steps = ref.shape[0]
+    gap = cfg["ny"] - 1
+    shear = abs(cfg["u_wall"][3][0] - cfg["u_wall"][2][0]) / gap
+    om_scale = shear if shear > 0 else max(np.abs(ref[..., 5]).max(), 1e-300)
+    res = {"steps": steps, "metrics": "pos/(NY-1), theta [rad], omega/shear rate"}
+    for name, st in (("F32", 1), ("F16S", 2), ("F64", 0)):
+        s = Solver([(dict(cfg, storage=st), parts)])
+        g = s.step(steps, record=True)
+        torch.cuda.synchronize()
+        s.close()
+        res[name] = {"pos": float(np.abs(g[..., 0:2] - ref[..., 0:2]).max() / gap),
+                     "theta": float(np.abs(g[..., 2] - ref[..., 2]).max()),
+                     "omega": float(np.abs(g[..., 5] - ref[..., 5]).max() / om_scale)}
+    return res
 
 
 # Launch shapes picked by the autotuner for the comparison workloads.

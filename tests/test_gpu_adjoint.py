@@ -217,3 +217,108 @@ def test_couette_256x64_gradients_match_oracle_fd(storage, tol):
             if abs(val - ref) > tol * abs(ref) + 2 * unc:
                 bad.append((key, name, val, ref, err))
     assert not bad, bad
+
+
+# ---------------------------------------------------------------------------
+# Several particles and channels: neighbour lists (overlapping adjoint
+# patches), shared tiles, batched channels.
+# ---------------------------------------------------------------------------
+def _multi():
+    ch0 = C.couette_config(48, 30, tau=0.8, storage=0)
+    ch0["gravity"] = [0.0, -2e-6]
+    e = shapes.ellipse(8.0, 2.0, n_markers=20, mode="param")
+    ci = shapes.circle(6.0, n_markers=18)
+    # bodies 4 lu apart: the probe stencils of each reach the other's patch
+    p0 = [C.particle(e, 15.2, 14.3, 0.2, density_ratio=1.2, u=0.001),
+          C.particle(ci, 26.1, 15.6, 0.0, density_ratio=1.1, v=0.0005)]
+    ch1 = C.base_config(24, 32, tau=0.8, bc_x=1, u_wall=[[0.0, 0.01], [0.0, -0.02], [0.0, 0.0], [0.0, 0.0]],
+                        body_force=[0.0, 1e-5], storage=0)
+    p1 = [C.particle(shapes.square(7.0), 11.7, 16.4, 0.1, density_ratio=1.3, omega=0.001)]
+    return [(ch0, p0), (ch1, p1)]
+
+
+def _gpu_adjoint_channels(chans, T, seeds):
+    from paper_1606_01805_amd import Solver
+
+    s = Solver(chans)
+    s.checkpoint_save(0)
+    s.step(T, record=False)
+    s.adjoint_begin(seeds, T)
+    s.adjoint_segment(0, T)
+    part, mk, wall = s.adjoint_gradients()
+    lam = [s.adjoint_field(ci) for ci in range(len(chans))]
+    s.close()
+    return part, mk, wall, lam
+
+
+def test_batched_multi_particle_adjoint_matches_fd_and_alone():
+    chans = _multi()
+    T = 10
+    rng = np.random.default_rng(21)
+    npart = sum(len(p) for _, p in chans)
+    seeds = np.zeros((npart, 10))
+    seeds[:, :6] = rng.standard_normal((npart, 6))
+    part, mk, wall, lam = _gpu_adjoint_channels(chans, T, seeds)
+    # batched == each channel alone, bitwise
+    o = 0
+    for ci, (cfg, ps) in enumerate(chans):
+        pa, mka, wa, la = _gpu_adjoint_channels([(cfg, ps)], T, seeds[o:o + len(ps)])
+        assert np.array_equal(pa, part[o:o + len(ps)])
+        for j in range(len(ps)):
+            assert np.array_equal(mka[j], mk[o + j])
+        assert np.array_equal(wa[0], wall[ci])
+        assert np.array_equal(la[0], lam[ci])
+        o += len(ps)
+    # against the oracle, channel by channel (the channels are independent;
+    # J of a channel is the seed-weighted sum over its particles)
+    bad = []
+    o = 0
+    for ci, (cfg, ps) in enumerate(chans):
+        c = seeds[o:o + len(ps), :6]
+
+        def objective(cf, pp, f0=None):
+            import oracle
+
+            orc = oracle.Oracle(cf)
+            for p in pp:
+                orc.add_particle(p)
+            orc.step(T, record=False)
+            return float((c * orc.particles()[:, :6]).sum()), orc.anchor_hash()
+
+        def deriv(perturb):
+            import copy
+
+            for h in (1e-3, 1e-4, 1e-5, 1e-6):
+                vals = []
+                for e in (-h, -h / 2, h / 2, h):
+                    cf, pp = copy.deepcopy(cfg), copy.deepcopy(ps)
+                    perturb(cf, pp, e)
+                    vals.append(objective(cf, pp))
+                if len({v[1] for v in vals}) == 1:
+                    d1 = (vals[3][0] - vals[0][0]) / (2 * h)
+                    d2 = (vals[2][0] - vals[1][0]) / h
+                    return (4 * d2 - d1) / 3
+            return None
+
+        for j in range(len(ps)):
+            g = part[o + j]
+            for name, key, val in (("x0", "x", g[0] + g[2]), ("y0", "y", g[1] + g[3]),
+                                   ("theta0", "theta", g[4] + g[5]), ("omega0", "omega", g[10] + g[11])):
+                def pert(cf, pp, e, j=j, key=key):
+                    pp[j][key] = float(pp[j][key]) + e
+                fd = deriv(pert)
+                assert fd is not None, (ci, j, name)
+                print(f"ch{ci} p{j} {name:7s} adjoint {val: .10e} fd {fd: .10e}")
+                if abs(val - fd) > TOL_R * abs(fd) + TOL_A:
+                    bad.append((ci, j, name, val, fd))
+
+            def pert_xi(cf, pp, e, j=j):
+                a = np.array(pp[j]["xi"], dtype=np.float64).copy()
+                a[3, 1] += e
+                pp[j]["xi"] = a
+            fd = deriv(pert_xi)
+            print(f"ch{ci} p{j} xi[3].y  adjoint {mk[o + j][3, 1]: .10e} fd {fd: .10e}")
+            if abs(mk[o + j][3, 1] - fd) > TOL_R * abs(fd) + TOL_A:
+                bad.append((ci, j, "xi[3].y", mk[o + j][3, 1], fd))
+        o += len(ps)
+    assert not bad, bad
