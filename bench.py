@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--persistent", type=int, default=None)
     ap.add_argument("--xcd-remap", type=int, default=None)
+    ap.add_argument("--overlap", type=int, default=None,
+                    help="1: lattice pass and surface stress in one launch (needs --tile-w 64)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the lattice launch shape with the project autotuner first")
     ap.add_argument("--no-variants", action="store_true",
@@ -262,6 +264,8 @@ def main():
         tuning["persistent_wgs"] = args.persistent
     if args.xcd_remap is not None:
         tuning["xcd_remap"] = args.xcd_remap
+    if args.overlap is not None:
+        tuning["overlap"] = args.overlap
 
     if args.copy_calibration:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")

@@ -123,9 +123,14 @@ typedef struct lbm_tuning {
     int32_t xcd_remap;       /* 1: hand each of the 8 XCDs (one L2 each) a
                                 contiguous block of tiles, so tiles that share
                                 halo cache lines run under the same L2 */
-    int32_t overlap;         /* 1: run the surface-stress / rigid-body kernel
-                                on a second stream, concurrently with the
-                                lattice pass (both need only the force stage) */
+    int32_t overlap;         /* 1: run the lattice pass and the surface-stress /
+                                rigid-body stage as one launch (both read only
+                                the step's input populations and force
+                                patches): the first workgroups take the
+                                particles, the rest take lattice tiles of
+                                64 x 9*rows_per_thread nodes.  Needs
+                                tile_w = 64 and persistent_wgs = 0 (else
+                                LBM_EINVAL); results are bitwise those of 0 */
 } lbm_tuning;
 
 typedef struct lbm_handle lbm_handle;
@@ -198,7 +203,8 @@ int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
  * [2] = surface stress and rigid-body update), measured with HIP events on the
  * handle's stream over `reps` back-to-back launches of each kernel alone.  The
  * launches run real steps, so the state advances by reps steps per kernel
- * phase; use a checkpoint around the call to keep it. */
+ * phase; use a checkpoint around the call to keep it.  With overlap = 1,
+ * out_us[1] times the combined launch without its particle workgroups. */
 int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]);
 
 /* ---- Discrete adjoint of the step (reverse-mode gradients) ----------------

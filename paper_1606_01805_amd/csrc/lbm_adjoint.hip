@@ -1220,12 +1220,14 @@ hipError_t launch_adj_ibm(int store, const AdjArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_adj_lattice(int store, const AdjArgs& a, int tile_w, int npt, hipStream_t s) {
-    const int chunks = 4 * npt;  // tiles hold 256 * npt nodes
+hipError_t launch_adj_lattice(int store, const AdjArgs& a, hipStream_t s) {
+    // one 64-node chunk per workgroup; tile widths are multiples of 64
+    if (a.s.tile_w % 64 != 0 || a.s.tile_h < 1) return hipErrorInvalidValue;
+    const int chunks = a.s.tile_w / 64 * a.s.tile_h;
     const long long grid = (long long)a.s.ntiles * chunks;
     if (grid <= 0) return hipSuccess;
     if (grid > INT_MAX) return hipErrorInvalidValue;
-#define L_(ST) adj_lattice_kernel<ST><<<(int)grid, 64, 0, s>>>(a, tile_w, chunks)
+#define L_(ST) adj_lattice_kernel<ST><<<(int)grid, 64, 0, s>>>(a, a.s.tile_w, chunks)
     ADJ_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();

@@ -48,8 +48,6 @@ struct lbm_handle {
     int store = 0;
     size_t elem = 8;
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;    // second stream for the particle kernel
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void* buf[2] = {nullptr, nullptr};
     void* ws_alloc = nullptr;
     size_t buf_bytes = 0;
@@ -175,12 +173,19 @@ extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) 
     return 2 * buffer_bytes(cfg, n, elem_size(cfg[0].storage));
 }
 
+// Tile height of the lattice pass: 256-thread workgroups cover
+// (256 / tile_w) * rows rows; the combined lattice / surface-stress launch
+// runs 64-wide tiles in workgroups of the particle kernel's size (9 waves).
+static int tile_height(const lbm_tuning& t) {
+    return t.overlap ? kIbmThreads / 64 * t.rows_per_thread : (256 / t.tile_w) * t.rows_per_thread;
+}
+
 static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     StepArgs a{};
     a.parity = parity < 0 ? cur : parity;
     a.tlist = h->dtlist;
     a.tile_w = h->tune.tile_w;
-    a.tile_h = (256 / h->tune.tile_w) * h->tune.rows_per_thread;
+    a.tile_h = tile_height(h->tune);
     a.fin = h->buf[cur];
     a.fout = h->buf[1 - cur];
     a.chan = h->dchan;
@@ -213,7 +218,7 @@ static void drop_graphs(lbm_handle* h) {
 }
 
 static int build_tiles(lbm_handle* h) {
-    const int tw = h->tune.tile_w, th = (256 / tw) * h->tune.rows_per_thread;
+    const int tw = h->tune.tile_w, th = tile_height(h->tune);
     h->htiles.clear();
     for (int c = 0; c < (int)h->cfg.size(); ++c) {
         h->hchan[c].tile0 = (int)h->htiles.size();
@@ -476,23 +481,22 @@ static int finalize(lbm_handle* h) {
     return LBM_OK;
 }
 
-static int enqueue_step(lbm_handle* h, int cur) {
-    StepArgs a = make_args(h, cur);
-    HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-    if (h->tune.overlap && h->nparts > 0 && h->side) {
-        // fork: the surface-stress kernel reads the force patches and the
-        // previous populations only, so it runs beside the lattice pass
-        HIPCHK(h, hipEventRecord(h->ev_fork, h->stream));
-        HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
-        HIPCHK(h, launch_traction(h->store, a, h->side));
-        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
-        HIPCHK(h, hipEventRecord(h->ev_join, h->side));
-        HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+// Lattice pass and surface stress of one step, after its force stage: two
+// launches, or one combined launch in the overlap mode.
+static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
+    if (h->tune.overlap) {
+        HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
     } else {
         HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
         HIPCHK(h, launch_traction(h->store, a, h->stream));
     }
     return LBM_OK;
+}
+
+static int enqueue_step(lbm_handle* h, int cur) {
+    StepArgs a = make_args(h, cur);
+    HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+    return enqueue_rest(h, a);
 }
 
 static int run_steps(lbm_handle* h, long long n) {
@@ -693,14 +697,9 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
     if (t->use_graph != 0 && t->use_graph != 1) FAIL(h, LBM_EINVAL, "use_graph must be 0 or 1");
     if (t->xcd_remap != 0 && t->xcd_remap != 1) FAIL(h, LBM_EINVAL, "xcd_remap must be 0 or 1");
     if (t->overlap != 0 && t->overlap != 1) FAIL(h, LBM_EINVAL, "overlap must be 0 or 1");
-    if (t->overlap && !h->side) {
-        // the second stream exists only for handles that ask for the overlap
-        if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
-            FAIL(h, LBM_EDEVICE, "creating the particle stream or its events failed");
-    }
-    const bool tiles = t->tile_w != h->tune.tile_w || t->rows_per_thread != h->tune.rows_per_thread;
+    if (t->overlap && (t->tile_w != 64 || t->persistent_wgs != 0))
+        FAIL(h, LBM_EINVAL, "overlap = 1 needs tile_w = 64 and persistent_wgs = 0");
+    const bool tiles = t->tile_w != h->tune.tile_w || tile_height(*t) != tile_height(h->tune);
     h->tune = *t;
     if (tiles) h->tiles_dirty = true;
     drop_graphs(h);
@@ -730,7 +729,13 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
             StepArgs a = make_args(h, h->cur, par0);
             if (k == 0) HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
             if (k == 1) {
-                HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+                if (h->tune.overlap) {
+                    // the combined launch without its particle workgroups
+                    a.nparts = 0;
+                    HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
+                } else {
+                    HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+                }
                 h->cur = 1 - h->cur;
             }
             if (k == 2) HIPCHK(h, launch_traction(h->store, a, h->stream));
@@ -897,8 +902,7 @@ extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
         a.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
         a.snap = h->tape_p + (size_t)t * np;  // particle snapshot after the force stage
         HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
-        HIPCHK(h, launch_traction(h->store, a, h->stream));
+        if ((r = enqueue_rest(h, a)) != LBM_OK) return r;
     }
     if (np)
         HIPCHK(h, hipMemcpyAsync(h->tape_p + (size_t)n * np, h->dparts, sizeof(PartDev) * np,
@@ -914,7 +918,7 @@ extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
         a.first = h->adj_first ? 1 : 0;
         HIPCHK(h, launch_adj_traction(h->store, a, h->stream));
         HIPCHK(h, launch_adj_ibm(h->store, a, h->stream));
-        HIPCHK(h, launch_adj_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+        HIPCHK(h, launch_adj_lattice(h->store, a, h->stream));
         h->lcur = 1 - h->lcur;
         h->apar = 1 - h->apar;
         h->adj_first = false;
@@ -999,10 +1003,6 @@ extern "C" int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;
     drop_graphs(h);
     free_adjoint(h);
-    if (h->side) (void)hipStreamSynchronize(h->side);
-    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-    if (h->side) (void)hipStreamDestroy(h->side);
     void* ptrs[] = {h->ws_alloc, h->dchan, h->dtiles, h->dparts, h->dxi, h->dnrm, h->dds, h->dpatch,
                     h->dcontrib, h->dmscr, h->dflags, h->dtlist, h->dstep, h->drec};
     for (void* p : ptrs)

@@ -89,6 +89,9 @@ hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx,
 hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s);
 hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hipStream_t s);
 hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s);
+// Lattice pass and surface stress in one launch (tile_w 64, tile_h 9 * npt,
+// no persistent workgroups).
+hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, hipStream_t s);
 hipError_t launch_fields(int store, const StepArgs& a, int chan, int nx, int ny, double* f_out,
                          double* rho, double* ux, double* uy, hipStream_t s);
 hipError_t launch_set_pop(int store, const StepArgs& a, int chan, int nx, int ny,
@@ -131,7 +134,7 @@ struct AdjArgs {
 
 hipError_t launch_adj_traction(int store, const AdjArgs& a, hipStream_t s);
 hipError_t launch_adj_ibm(int store, const AdjArgs& a, hipStream_t s);
-hipError_t launch_adj_lattice(int store, const AdjArgs& a, int tile_w, int npt, hipStream_t s);
+hipError_t launch_adj_lattice(int store, const AdjArgs& a, hipStream_t s);
 hipError_t launch_adj_finish(int store, const AdjArgs& a, int chan, int with_init, double* out8,
                              hipStream_t s);
 hipError_t launch_adj_field(int store, const AdjArgs& a, int chan, double* out, hipStream_t s);

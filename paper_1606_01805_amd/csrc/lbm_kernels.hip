@@ -22,6 +22,7 @@
 // The FP32 and FP16S forms keep the deviation d_i = f_i - w_i and compute in
 // FP32.  The immersed-boundary and rigid-body stages are FP64 in every form.
 #include <algorithm>
+#include <climits>
 
 #include "lbm_device.h"
 
@@ -271,15 +272,90 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
     }
 }
 
+// One tile of the lattice pass: lane (lx, ly) of a TW-wide workgroup handles
+// NPT consecutive rows of column x0 + lx.
 template <int ST, int TW, int NPT>
-__global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
+__device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, int ly) {
     using T = typename Sto<ST>::T;
     const T* __restrict__ fin = (const T*)a.fin;
     T* __restrict__ fout = (T*)a.fout;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    const int stride = a.persistent ? (int)gridDim.x : a.ntiles;
     const int* tl_cur = a.tlist + (long long)a.parity * a.ntiles * kTileList;
     int* tl_next = a.tlist + (long long)(1 - a.parity) * a.ntiles * kTileList;
+    const TileDev* tp = a.tiles + t;
+    const int tx0 = uni(tp->x0), ty0 = uni(tp->y0);
+    const ChanDev c = load_chan(a.chan + uni(tp->chan));
+    const int x = tx0 + lx;
+    const int xl = x < c.nx ? x : c.nx - 1;  // loads of lanes past the edge stay in bounds
+    // Particles whose force patches overlap this tile, appended by the
+    // particle kernel of this step; sorted ascending and deduplicated so
+    // overlapping patches add in a fixed order.  The other half of the
+    // list store is reset for the next step.
+    const int* e = tl_cur + (long long)t * kTileList;
+    const int cnt = uni(e[0]);
+    if (threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
+    int list[kTileList - 1];
+    int nlist = 0;
+    if (cnt > kTileList - 1) {
+        nlist = kTileList;  // more patches than slots: scan the channel's particles
+    } else {
+        for (int j = 0; j < cnt; ++j) {
+            const int v = uni(e[1 + j]);
+            int k = nlist;
+            bool dup = false;
+            for (int m = 0; m < nlist; ++m) dup |= list[m] == v;
+            if (dup) continue;
+            while (k > 0 && list[k - 1] > v) {
+                list[k] = list[k - 1];
+                --k;
+            }
+            list[k] = v;
+            ++nlist;
+        }
+    }
+    // all pulls of the thread's rows first, then collide and store
+    if constexpr (ST == ST_F64) {
+        double f[NPT][9];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int y = ty0 + ly * NPT + r;
+            const int yl = y < c.ny ? y : c.ny - 1;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                int xs, ys;
+                pull_src(c, i, xl, yl, xs, ys);
+                f[r][i] = fin[pidx(c, i, ys, xs)];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int y = ty0 + ly * NPT + r;
+            if (x < c.nx && y < c.ny) collide_store_f64(a, c, x, y, f[r], list, nlist, fout);
+        }
+    } else {
+        float d[NPT][9];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int y = ty0 + ly * NPT + r;
+            const int yl = y < c.ny ? y : c.ny - 1;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                int xs, ys;
+                pull_src(c, i, xl, yl, xs, ys);
+                d[r][i] = load_dev<ST>(fin, pidx(c, i, ys, xs), i, c);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int y = ty0 + ly * NPT + r;
+            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, x, y, d[r], list, nlist, fout);
+        }
+    }
+}
+
+template <int ST, int TW, int NPT>
+__global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int stride = a.persistent ? (int)gridDim.x : a.ntiles;
     // Workgroups are dispatched round-robin over the 8 XCDs.  With the remap
     // (one workgroup per tile, grid rounded up to a multiple of 8) XCD x
     // takes the contiguous tile block [x * per, (x + 1) * per).
@@ -288,77 +364,7 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
         const int per = (int)gridDim.x / 8;
         t0 = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     }
-    for (int t = t0; t < a.ntiles; t += stride) {
-        const TileDev* tp = a.tiles + t;
-        const int tx0 = uni(tp->x0), ty0 = uni(tp->y0);
-        const ChanDev c = load_chan(a.chan + uni(tp->chan));
-        const int x = tx0 + lx;
-        const int xl = x < c.nx ? x : c.nx - 1;  // loads of lanes past the edge stay in bounds
-        // Particles whose force patches overlap this tile, appended by the
-        // particle kernel of this step; sorted ascending and deduplicated so
-        // overlapping patches add in a fixed order.  The other half of the
-        // list store is reset for the next step.
-        const int* e = tl_cur + (long long)t * kTileList;
-        const int cnt = uni(e[0]);
-        if (threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
-        int list[kTileList - 1];
-        int nlist = 0;
-        if (cnt > kTileList - 1) {
-            nlist = kTileList;  // more patches than slots: scan the channel's particles
-        } else {
-            for (int j = 0; j < cnt; ++j) {
-                const int v = uni(e[1 + j]);
-                int k = nlist;
-                bool dup = false;
-                for (int m = 0; m < nlist; ++m) dup |= list[m] == v;
-                if (dup) continue;
-                while (k > 0 && list[k - 1] > v) {
-                    list[k] = list[k - 1];
-                    --k;
-                }
-                list[k] = v;
-                ++nlist;
-            }
-        }
-        // all pulls of the thread's rows first, then collide and store
-        if constexpr (ST == ST_F64) {
-            double f[NPT][9];
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                const int y = ty0 + ly * NPT + r;
-                const int yl = y < c.ny ? y : c.ny - 1;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    int xs, ys;
-                    pull_src(c, i, xl, yl, xs, ys);
-                    f[r][i] = fin[pidx(c, i, ys, xs)];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                const int y = ty0 + ly * NPT + r;
-                if (x < c.nx && y < c.ny) collide_store_f64(a, c, x, y, f[r], list, nlist, fout);
-            }
-        } else {
-            float d[NPT][9];
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                const int y = ty0 + ly * NPT + r;
-                const int yl = y < c.ny ? y : c.ny - 1;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    int xs, ys;
-                    pull_src(c, i, xl, yl, xs, ys);
-                    d[r][i] = load_dev<ST>(fin, pidx(c, i, ys, xs), i, c);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                const int y = ty0 + ly * NPT + r;
-                if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, x, y, d[r], list, nlist, fout);
-            }
-        }
-    }
+    for (int t = t0; t < a.ntiles; t += stride) lattice_tile<ST, TW, NPT>(a, t, lx, ly);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,13 +374,12 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
 // probe's MLS value and gradient weights and the marker's traction.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
+__device__ __forceinline__ void traction_body(const StepArgs& a, int b) {
     __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double s_t[3][1024];
     __shared__ double sums[3];
     const int tid = threadIdx.x;
-    if ((int)blockIdx.x >= a.nparts) return;
-    PartDev* P = a.parts + blockIdx.x;
+    PartDev* P = a.parts + b;
     const ChanDev& c = a.chan[P->chan];
     const int nm = P->nm, mb = P->mbeg;
     const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
@@ -531,7 +536,7 @@ __global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
     P->F[1] = Fy;
     P->M = Mz;
     const long long step = *a.dstep - 1;
-    double* r = a.rec + ((step % kRecSlots) * a.nparts + blockIdx.x) * 10;
+    double* r = a.rec + ((step % kRecSlots) * a.nparts + b) * 10;
     r[0] = nX0;
     r[1] = nX1;
     r[2] = nth;
@@ -548,6 +553,33 @@ __global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
         a.flags[0] = 1;
         atomicMin(&a.flags[1], (int)step);
     }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
+    if ((int)blockIdx.x < a.nparts) traction_body<ST>(a, (int)blockIdx.x);
+}
+
+// The surface stress of step n reads the populations entering the step and
+// the force patches of the step, the lattice pass reads the same and writes
+// only the populations leaving it, so the two share one launch: workgroups
+// [0, tb) take the particles (tb = nparts rounded up to a multiple of 8, so
+// that lattice workgroup j lands on XCD j mod 8 as in the lattice kernel)
+// and the rest take lattice tiles of 64 x 9*NPT nodes.  The particle
+// workgroups are dispatched first and run alongside the lattice tiles.
+template <int ST, int NPT>
+__global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs a, int tb) {
+    const int j = (int)blockIdx.x - tb;
+    if (j < 0) {
+        if ((int)blockIdx.x < a.nparts) traction_body<ST>(a, (int)blockIdx.x);
+        return;
+    }
+    int t = j;
+    if (a.xcd_remap) {
+        const int per = ((int)gridDim.x - tb) / 8;
+        t = (j % 8) * per + j / 8;
+    }
+    if (t < a.ntiles) lattice_tile<ST, 64, NPT>(a, t, (int)threadIdx.x % 64, (int)threadIdx.x / 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,6 +761,29 @@ hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s) {
     LBM_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t lattice_traction_dispatch(const StepArgs& a, int npt, int tb, int grid,
+                                            hipStream_t s) {
+    if (npt == 1) lattice_traction_kernel<ST, 1><<<grid, kIbmThreads, 0, s>>>(a, tb);
+    else if (npt == 2) lattice_traction_kernel<ST, 2><<<grid, kIbmThreads, 0, s>>>(a, tb);
+    else lattice_traction_kernel<ST, 4><<<grid, kIbmThreads, 0, s>>>(a, tb);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, hipStream_t s) {
+    if (a.persistent > 0 || a.tile_w != 64 || a.tile_h != 9 * npt) return hipErrorInvalidValue;
+    const long long tb = a.nparts > 0 ? ((long long)a.nparts + 7) / 8 * 8 : 0;
+    const long long tl = a.xcd_remap ? ((long long)a.ntiles + 7) / 8 * 8 : a.ntiles;
+    const long long grid = tb + tl;
+    if (grid <= 0) return hipSuccess;
+    if (grid > INT_MAX) return hipErrorInvalidValue;
+    switch (store) {
+        case ST_F64: return lattice_traction_dispatch<ST_F64>(a, npt, (int)tb, (int)grid, s);
+        case ST_F32: return lattice_traction_dispatch<ST_F32>(a, npt, (int)tb, (int)grid, s);
+        default: return lattice_traction_dispatch<ST_F16S>(a, npt, (int)tb, (int)grid, s);
+    }
 }
 
 hipError_t launch_fields(int store, const StepArgs& a, int chan, int nx, int ny, double* f_out,

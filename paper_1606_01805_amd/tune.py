@@ -1,5 +1,6 @@
 """Autotuner of the lattice-pass launch shape (tile width, rows per thread,
-persistent grid, XCD-aware tile order).
+persistent grid, XCD-aware tile order, lattice pass and surface stress
+combined in one launch or not).
 
 Each candidate is timed on whole steps of the caller's own solver (all three
 kernels, graph-replayed), from a checkpoint that is restored afterwards, so
@@ -23,10 +24,13 @@ def candidates(n_nodes):
     for tw in (64, 128, 256):
         for rows in (1, 2, 4):
             for remap in (0, 1):
-                out.append(dict(tile_w=tw, rows_per_thread=rows, persistent_wgs=0, xcd_remap=remap))
+                out.append(dict(tile_w=tw, rows_per_thread=rows, persistent_wgs=0, xcd_remap=remap, overlap=0))
+    for rows in (1, 2, 4):  # lattice pass and surface stress in one launch
+        for remap in (0, 1):
+            out.append(dict(tile_w=64, rows_per_thread=rows, persistent_wgs=0, xcd_remap=remap, overlap=1))
     if n_nodes > 4_000_000:  # persistent grids only pay off on big lattices
         for wgs in (1024, 2048, 4096):
-            out.append(dict(tile_w=256, rows_per_thread=2, persistent_wgs=wgs, xcd_remap=0))
+            out.append(dict(tile_w=256, rows_per_thread=2, persistent_wgs=wgs, xcd_remap=0, overlap=0))
     return out
 
 

@@ -141,8 +141,10 @@ def test_adjoint_launch_shape_independent():
     c = np.random.default_rng(6).standard_normal(6)
     a = gpu_adjoint(cfg, parts, 8, c)
     b = gpu_adjoint(cfg, parts, 8, c, tuning=dict(tile_w=64, rows_per_thread=2))
-    for x, y in zip(a, b):
+    d = gpu_adjoint(cfg, parts, 8, c, tuning=dict(tile_w=64, rows_per_thread=2, overlap=1))
+    for x, y, z in zip(a, b, d):
         assert np.array_equal(x, y)
+        assert np.array_equal(x, z)
 
 
 @pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 1e-3), (C.STORE_F16S, 3e-2)])

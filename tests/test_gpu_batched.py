@@ -68,6 +68,16 @@ def test_batched_persistent_grid_bitwise():
     assert np.array_equal(a, b)
 
 
+def test_batched_combined_launch_bitwise():
+    """Channels of uneven size with the lattice pass and the surface stress in
+    one launch: bitwise the separate launches."""
+    chans = _small_ensemble(C.STORE_F32)
+    _, a = run_gpu(chans, 120)
+    for remap in (0, 1):
+        _, b = run_gpu(chans, 120, tuning=dict(overlap=1, tile_w=64, rows_per_thread=1, xcd_remap=remap))
+        assert np.array_equal(a, b)
+
+
 def test_full_ensemble_sampled_channels():
     """The 256-channel ensemble at full size, in the launch configuration of
     the benchmark: every particle record is finite, and 4 sampled channels

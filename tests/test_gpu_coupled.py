@@ -137,16 +137,53 @@ def test_couette_reduced_forms_trajectory_error(storage, tol):
 
 
 def test_determinism_and_graph_vs_eager():
-    """Runs are bitwise reproducible, and neither graph replay nor running the
-    particle kernel beside the lattice pass changes a bit."""
+    """Runs are bitwise reproducible, and neither graph replay nor the
+    combined lattice / surface-stress launch (any rows, either tile order)
+    changes a bit."""
     wl = C.couette(storage=C.STORE_F32)
     _, a = run_gpu(wl.channels, 301)
     _, b = run_gpu(wl.channels, 301)
     _, c = run_gpu(wl.channels, 301, tuning=dict(use_graph=0))
-    _, d = run_gpu(wl.channels, 301, tuning=dict(overlap=0))
-    _, e = run_gpu(wl.channels, 301, tuning=dict(overlap=0, use_graph=0))
-    for x in (b, c, d, e):
+    xs = [b, c]
+    for rows in (1, 2, 4):
+        for remap in (0, 1):
+            xs.append(run_gpu(wl.channels, 301, tuning=dict(overlap=1, tile_w=64, rows_per_thread=rows,
+                                                            xcd_remap=remap))[1])
+    xs.append(run_gpu(wl.channels, 301, tuning=dict(overlap=1, tile_w=64, use_graph=0))[1])
+    for x in xs:
         assert np.array_equal(a, x)
+
+
+def test_combined_launch_fp64_parity_with_overlapping_patches():
+    """The combined lattice / surface-stress launch with three particles, two
+    of them with overlapping patches (FP64): oracle parity, and bitwise the
+    records of the separate launches."""
+    cfg = C.couette_config(120, 60, storage=C.STORE_F64)
+    a = C.particle(shapes.circle(10.0, n_markers=32), 40.2, 30.1, 0.0)
+    b = C.particle(shapes.square(9.0), 53.7, 31.4, 0.3)
+    c = C.particle(shapes.triangle(10.0), 90.0, 22.0, 1.0)
+    chans = [(cfg, [a, b, c])]
+    tun = dict(overlap=1, tile_w=64, rows_per_thread=2)
+    errs = _compare(chans, 400, tuning=tun)
+    for e in errs:
+        assert max(e.values()) < 1e-11, errs
+    _, g = run_gpu(chans, 200, tuning=tun)
+    _, h = run_gpu(chans, 200)
+    assert np.array_equal(g, h)
+
+
+def test_combined_launch_rejects_other_shapes():
+    from paper_1606_01805_amd import Solver
+
+    wl = C.couette(storage=C.STORE_F32)
+    s = Solver(wl.channels)
+    with pytest.raises(RuntimeError, match="overlap"):
+        s.set_tuning(overlap=1, tile_w=256)
+    with pytest.raises(RuntimeError, match="overlap"):
+        s.set_tuning(overlap=1, tile_w=64, persistent_wgs=16)
+    s.set_tuning(overlap=1, tile_w=64)
+    s.step(3)
+    s.close()
 
 
 def test_checkpoint_restore_replays_bitwise():

@@ -64,11 +64,15 @@ def test_side_walls_bitwise():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("tile_w,npt,pers", [(64, 1, 0), (128, 2, 0), (256, 4, 0), (64, 4, 7), (256, 1, 3)])
-def test_launch_shapes_do_not_change_results(tile_w, npt, pers):
+@pytest.mark.parametrize("tile_w,npt,pers,ov", [(64, 1, 0, 0), (128, 2, 0, 0), (256, 4, 0, 0), (64, 4, 7, 0),
+                                                (256, 1, 3, 0), (64, 1, 0, 1), (64, 2, 0, 1), (64, 4, 0, 1)])
+def test_launch_shapes_do_not_change_results(tile_w, npt, pers, ov):
+    """Tile shape, persistent grid and the combined lattice / surface-stress
+    launch (ov = 1, 64 x 9*npt tiles) give bitwise the same populations."""
     cfg = C.base_config(130, 45, tau=0.8, bc_y=1, body_force=[1e-6, 0.0])
     f = None
-    a, _ = _lattice_pair(cfg, 40, f, tuning=dict(tile_w=tile_w, rows_per_thread=npt, persistent_wgs=pers))
+    a, _ = _lattice_pair(cfg, 40, f, tuning=dict(tile_w=tile_w, rows_per_thread=npt, persistent_wgs=pers,
+                                                 overlap=ov))
     b, _ = _lattice_pair(cfg, 40, f)
     assert np.array_equal(a, b)
 
