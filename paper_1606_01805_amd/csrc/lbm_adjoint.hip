@@ -126,7 +126,7 @@ __device__ __forceinline__ CollAdj collide_adj(const double lfc[9], double rho, 
     return r;
 }
 
-// Transpose of the Zou-He closure of zouhe_f64 at one wall node.  fr holds
+// Transpose of the Zou-He closure of walls_f64 at one wall node.  fr holds
 // the streamed (known) populations; L the adjoint of the closed populations,
 // replaced by the adjoint of the streamed ones (zero for the three unknowns,
 // which the closure overwrites).  Adds the wall-velocity derivatives.
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
     // latency overlaps the end of the kernel)
     StepArgs sa = a.s;
     sa.tlist = a.atlist;
-    mark_tiles(sa, c, ax0u, ay0u, aw, ah, tid, blockDim.x);
+    mark_tiles(sa, c, (int)blockIdx.x, ax0u, ay0u, aw, ah, tid, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------

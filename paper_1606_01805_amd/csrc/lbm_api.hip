@@ -65,14 +65,19 @@ struct lbm_handle {
     double2* dnrm = nullptr;
     double* dds = nullptr;
     double2* dpatch = nullptr;
-    double2* dcontrib = nullptr;
+    int2* dwork = nullptr;         // particle-kernel workgroups (particle, round)
+    int nwork = 0;
+    int2* dpsum = nullptr;         // partial-patch sum chunks (particle, first cell)
+    int npsum = 0;
+    int* dpcount = nullptr;        // [nparts] completion counters
+    double2* dpartial = nullptr;   // per-round partial patches of particles of several rounds
     double* dmscr = nullptr;
     int* dflags = nullptr;
     int* dtlist = nullptr;
     long long* dstep = nullptr;
     double* drec = nullptr;
     int nparts = 0;
-    int max_cells = kMaxCellsDefault;
+    int max_cells = kMaxCells;
     int cur = 0;
     long long steps = 0;
     bool finalized = false;
@@ -200,7 +205,12 @@ static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     a.nrm = h->dnrm;
     a.ds = h->dds;
     a.patch = h->dpatch;
-    a.contrib = h->dcontrib;
+    a.work = h->dwork;
+    a.nwork = h->nwork;
+    a.psum = h->dpsum;
+    a.npsum = h->npsum;
+    a.pcount = h->dpcount;
+    a.partial = h->dpartial;
     a.mscr = h->dmscr;
     a.flags = h->dflags;
     a.dstep = h->dstep;
@@ -316,16 +326,6 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
         h->buf[0] = h->ws_alloc;
     }
     h->buf[1] = (char*)h->buf[0] + h->buf_bytes;
-    {
-        // Force-patch capacity: the spreading kernel keeps one 64-bit marker
-        // mask per patch cell in LDS next to its static buffers.
-        int dev = 0, maxsh = 65536;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
-            long long avail = (long long)maxsh - (long long)ibm_static_lds_bytes() - (long long)ibm_lds_bytes(0) - 1024;
-            h->max_cells = (int)std::max(1024LL, std::min(32768LL, avail / 8));
-        }
-    }
     long long off = 0;
     h->hchan.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -373,7 +373,7 @@ extern "C" int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_partic
     if (h->finalized) FAIL(h, LBM_ESTATE, "particles can only be added before the first step");
     if (!d || channel < 0 || channel >= (int)h->cfg.size()) FAIL(h, LBM_EINVAL, "bad channel or descriptor");
     const int n = d->n_markers;
-    if (n < 3 || n > 1024) FAIL(h, LBM_EINVAL, "n_markers must be in 3..1024");
+    if (n < 3 || n > kMaxMarkers) FAIL(h, LBM_EINVAL, "n_markers must be in 3..%d", kMaxMarkers);
     if (!d->xi || !d->nrm || !d->ds) FAIL(h, LBM_EINVAL, "marker arrays must not be NULL");
     double sc[9] = {d->x, d->y, d->theta, d->u, d->v, d->omega, d->density_ratio, d->area, d->polar_moment};
     if (!finite_all(sc, 9) || !finite_all(d->xi, 2 * (size_t)n) || !finite_all(d->nrm, 2 * (size_t)n) ||
@@ -466,8 +466,32 @@ static int finalize(lbm_handle* h) {
     HIPCHK(h, hipMalloc(&h->dnrm, sizeof(double2) * nmk));
     HIPCHK(h, hipMalloc(&h->dds, sizeof(double) * nmk));
     HIPCHK(h, hipMalloc(&h->dpatch, sizeof(double2) * std::max<long long>(cells, 1)));
-    HIPCHK(h, hipMalloc(&h->dcontrib, sizeof(double2) * 9 * nmk));
     HIPCHK(h, hipMalloc(&h->dmscr, sizeof(double) * 4 * nmk));
+    // Particle-kernel work: one workgroup per round of kRound markers in both
+    // particle kernels.  A particle of several rounds gets one partial force
+    // patch per round, summed by chunks of 256 cells.
+    std::vector<int2> work, psum;
+    long long pcells = 0;
+    for (int k = 0; k < np; ++k) {
+        const int nr = (pd[k].nm + kRound - 1) / kRound;
+        for (int r = 0; r < nr; ++r) work.push_back(make_int2(k, r));
+        pd[k].part_off = pcells;
+        if (nr > 1) {
+            pcells += (long long)nr * pd[k].patch_cap;
+            for (int q = 0; q < pd[k].patch_cap; q += 256) psum.push_back(make_int2(k, q));
+        }
+    }
+    h->nwork = (int)work.size();
+    h->npsum = (int)psum.size();
+    HIPCHK(h, hipMalloc(&h->dpartial, sizeof(double2) * std::max<long long>(pcells, 1)));
+    HIPCHK(h, hipMalloc(&h->dwork, sizeof(int2) * std::max<size_t>(work.size(), 1)));
+    HIPCHK(h, hipMalloc(&h->dpsum, sizeof(int2) * std::max<size_t>(psum.size(), 1)));
+    HIPCHK(h, hipMalloc(&h->dpcount, sizeof(int) * std::max(np, 1)));
+    HIPCHK(h, hipMemset(h->dpcount, 0, sizeof(int) * std::max(np, 1)));
+    if (!work.empty())
+        HIPCHK(h, hipMemcpy(h->dwork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
+    if (!psum.empty())
+        HIPCHK(h, hipMemcpy(h->dpsum, psum.data(), sizeof(int2) * psum.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMalloc(&h->drec, sizeof(double) * 10 * kRecSlots * std::max(np, 1)));
     if (np) {
         HIPCHK(h, hipMemcpy(h->dparts, pd.data(), sizeof(PartDev) * np, hipMemcpyHostToDevice));
@@ -496,6 +520,7 @@ static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
 static int enqueue_step(lbm_handle* h, int cur) {
     StepArgs a = make_args(h, cur);
     HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+    HIPCHK(h, launch_patch_sum(a, h->stream));
     return enqueue_rest(h, a);
 }
 
@@ -727,11 +752,14 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
         HIPCHK(h, hipEventRecord(e0, h->stream));
         for (int i = 0; i < reps; ++i) {
             StepArgs a = make_args(h, h->cur, par0);
-            if (k == 0) HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+            if (k == 0) {
+                HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+                HIPCHK(h, launch_patch_sum(a, h->stream));
+            }
             if (k == 1) {
                 if (h->tune.overlap) {
                     // the combined launch without its particle workgroups
-                    a.nparts = 0;
+                    a.nwork = 0;
                     HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
                 } else {
                     HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
@@ -902,6 +930,7 @@ extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
         a.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
         a.snap = h->tape_p + (size_t)t * np;  // particle snapshot after the force stage
         HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+        HIPCHK(h, launch_patch_sum(a, h->stream));
         if ((r = enqueue_rest(h, a)) != LBM_OK) return r;
     }
     if (np)
@@ -1004,7 +1033,8 @@ extern "C" int lbm_destroy(lbm_handle* h) {
     drop_graphs(h);
     free_adjoint(h);
     void* ptrs[] = {h->ws_alloc, h->dchan, h->dtiles, h->dparts, h->dxi, h->dnrm, h->dds, h->dpatch,
-                    h->dcontrib, h->dmscr, h->dflags, h->dtlist, h->dstep, h->drec};
+                    h->dmscr, h->dflags, h->dtlist, h->dstep, h->drec,
+                    h->dwork, h->dpsum, h->dpcount, h->dpartial};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& c : h->ck) {

@@ -108,48 +108,64 @@ __device__ __forceinline__ ChanDev load_chan(const ChanDev* p) {
 // Zou-He known-velocity wall (Sec. 1.1): mass and normal momentum fix rho,
 // bounce-back of the non-equilibrium normal population, tangential momentum
 // for the two diagonals; target momentum m = rho u_w - g/2.
-__device__ __forceinline__ void zouhe_f64(int side, double f[9], double uwx, double uwy,
-                                          double gx, double gy) {
-    double rho, mx, my;
-    if (side == 2) {
-        rho = (f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]) - 0.5 * gy) / (1.0 - uwy);
-        mx = rho * uwx - 0.5 * gx;
-        my = rho * uwy - 0.5 * gy;
-        f[2] = f[4] + 2.0 * my / 3.0;
-        f[5] = f[7] - 0.5 * (f[1] - f[3]) + 0.5 * mx + my / 6.0;
-        f[6] = f[8] + 0.5 * (f[1] - f[3]) - 0.5 * mx + my / 6.0;
-    } else if (side == 3) {
-        rho = (f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]) + 0.5 * gy) / (1.0 + uwy);
-        mx = rho * uwx - 0.5 * gx;
-        my = rho * uwy - 0.5 * gy;
-        f[4] = f[2] - 2.0 * my / 3.0;
-        f[7] = f[5] + 0.5 * (f[1] - f[3]) - 0.5 * mx - my / 6.0;
-        f[8] = f[6] - 0.5 * (f[1] - f[3]) + 0.5 * mx - my / 6.0;
-    } else if (side == 0) {
-        rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7]) - 0.5 * gx) / (1.0 - uwx);
-        mx = rho * uwx - 0.5 * gx;
-        my = rho * uwy - 0.5 * gy;
-        f[1] = f[3] + 2.0 * mx / 3.0;
-        f[5] = f[7] - 0.5 * (f[2] - f[4]) + mx / 6.0 + 0.5 * my;
-        f[8] = f[6] + 0.5 * (f[2] - f[4]) + mx / 6.0 - 0.5 * my;
-    } else {
-        rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8]) + 0.5 * gx) / (1.0 + uwx);
-        mx = rho * uwx - 0.5 * gx;
-        my = rho * uwy - 0.5 * gy;
-        f[3] = f[1] - 2.0 * mx / 3.0;
-        f[7] = f[5] + 0.5 * (f[2] - f[4]) - mx / 6.0 - 0.5 * my;
-        f[6] = f[8] - 0.5 * (f[2] - f[4]) - mx / 6.0 + 0.5 * my;
-    }
-}
-
+// Zou-He closures of the four walls (node on the wall, known wall velocity
+// u_w, body force g): the unknown populations follow from the density and
+// the target momentum m = rho u_w - g/2, with the bounce-back of the
+// non-equilibrium normal part.  Each axis is one pass that evaluates both
+// of its walls' closures from the incoming populations and selects per
+// lane, so the arrays are only ever indexed by constants (a store behind a
+// per-lane branch can be merged by the compiler into one store at a computed
+// index, which sends the whole array to private memory).  The pass runs only
+// if a lane of the wave lies on one of its walls.
 __device__ __forceinline__ void walls_f64(const ChanDev& c, int x, int y, double f[9]) {
-    if (c.bcy == 1) {
-        if (y == 0) zouhe_f64(2, f, c.uw[2][0], c.uw[2][1], c.g[0], c.g[1]);
-        else if (y == c.ny - 1) zouhe_f64(3, f, c.uw[3][0], c.uw[3][1], c.g[0], c.g[1]);
+    const double gx = c.g[0], gy = c.g[1];
+    const bool s2 = c.bcy == 1 && y == 0;
+    const bool s3 = c.bcy == 1 && !s2 && y == c.ny - 1;
+    if (__any(s2 || s3)) {
+        // y = 0 (side 2): unknowns 2, 5, 6
+        double rho = (f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]) - 0.5 * gy) / (1.0 - c.uw[2][1]);
+        double mx = rho * c.uw[2][0] - 0.5 * gx;
+        double my = rho * c.uw[2][1] - 0.5 * gy;
+        const double a2 = f[4] + 2.0 * my / 3.0;
+        const double a5 = f[7] - 0.5 * (f[1] - f[3]) + 0.5 * mx + my / 6.0;
+        const double a6 = f[8] + 0.5 * (f[1] - f[3]) - 0.5 * mx + my / 6.0;
+        // y = ny - 1 (side 3): unknowns 4, 7, 8
+        rho = (f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]) + 0.5 * gy) / (1.0 + c.uw[3][1]);
+        mx = rho * c.uw[3][0] - 0.5 * gx;
+        my = rho * c.uw[3][1] - 0.5 * gy;
+        const double b4 = f[2] - 2.0 * my / 3.0;
+        const double b7 = f[5] + 0.5 * (f[1] - f[3]) - 0.5 * mx - my / 6.0;
+        const double b8 = f[6] - 0.5 * (f[1] - f[3]) + 0.5 * mx - my / 6.0;
+        f[2] = s2 ? a2 : f[2];
+        f[5] = s2 ? a5 : f[5];
+        f[6] = s2 ? a6 : f[6];
+        f[4] = s3 ? b4 : f[4];
+        f[7] = s3 ? b7 : f[7];
+        f[8] = s3 ? b8 : f[8];
     }
-    if (c.bcx == 1) {
-        if (x == 0) zouhe_f64(0, f, c.uw[0][0], c.uw[0][1], c.g[0], c.g[1]);
-        else if (x == c.nx - 1) zouhe_f64(1, f, c.uw[1][0], c.uw[1][1], c.g[0], c.g[1]);
+    const bool s0 = c.bcx == 1 && x == 0;
+    const bool s1 = c.bcx == 1 && !s0 && x == c.nx - 1;
+    if (__any(s0 || s1)) {
+        // x = 0 (side 0): unknowns 1, 5, 8
+        double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7]) - 0.5 * gx) / (1.0 - c.uw[0][0]);
+        double mx = rho * c.uw[0][0] - 0.5 * gx;
+        double my = rho * c.uw[0][1] - 0.5 * gy;
+        const double a1 = f[3] + 2.0 * mx / 3.0;
+        const double a5 = f[7] - 0.5 * (f[2] - f[4]) + mx / 6.0 + 0.5 * my;
+        const double a8 = f[6] + 0.5 * (f[2] - f[4]) + mx / 6.0 - 0.5 * my;
+        // x = nx - 1 (side 1): unknowns 3, 7, 6
+        rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8]) + 0.5 * gx) / (1.0 + c.uw[1][0]);
+        mx = rho * c.uw[1][0] - 0.5 * gx;
+        my = rho * c.uw[1][1] - 0.5 * gy;
+        const double b3 = f[1] - 2.0 * mx / 3.0;
+        const double b7 = f[5] + 0.5 * (f[2] - f[4]) - mx / 6.0 - 0.5 * my;
+        const double b6 = f[8] - 0.5 * (f[2] - f[4]) - mx / 6.0 + 0.5 * my;
+        f[1] = s0 ? a1 : f[1];
+        f[5] = s0 ? a5 : f[5];
+        f[8] = s0 ? a8 : f[8];
+        f[3] = s1 ? b3 : f[3];
+        f[7] = s1 ? b7 : f[7];
+        f[6] = s1 ? b6 : f[6];
     }
 }
 
@@ -176,59 +192,64 @@ __device__ __forceinline__ void store_dev(typename Sto<ST>::T* p, long long k, i
     }
 }
 
-// The Zou-He closure of zouhe_f64 written for deviations: the weights of the
-// known populations entering rho sum to 1, and w_i cancels in every
-// difference.
-__device__ __forceinline__ void zouhe_dev(int side, float d[9], float uwx, float uwy, float gx,
-                                          float gy) {
-    float drho, rho, mx, my;
-    if (side == 2) {
-        float s = d[0] + d[1] + d[3] + 2.0f * (d[4] + d[7] + d[8]);
-        drho = (s - 0.5f * gy + uwy) / (1.0f - uwy);
-        rho = 1.0f + drho;
-        mx = rho * uwx - 0.5f * gx;
-        my = rho * uwy - 0.5f * gy;
-        d[2] = d[4] + (2.0f / 3.0f) * my;
-        d[5] = d[7] - 0.5f * (d[1] - d[3]) + 0.5f * mx + my * (1.0f / 6.0f);
-        d[6] = d[8] + 0.5f * (d[1] - d[3]) - 0.5f * mx + my * (1.0f / 6.0f);
-    } else if (side == 3) {
-        float s = d[0] + d[1] + d[3] + 2.0f * (d[2] + d[5] + d[6]);
-        drho = (s + 0.5f * gy - uwy) / (1.0f + uwy);
-        rho = 1.0f + drho;
-        mx = rho * uwx - 0.5f * gx;
-        my = rho * uwy - 0.5f * gy;
-        d[4] = d[2] - (2.0f / 3.0f) * my;
-        d[7] = d[5] + 0.5f * (d[1] - d[3]) - 0.5f * mx - my * (1.0f / 6.0f);
-        d[8] = d[6] - 0.5f * (d[1] - d[3]) + 0.5f * mx - my * (1.0f / 6.0f);
-    } else if (side == 0) {
-        float s = d[0] + d[2] + d[4] + 2.0f * (d[3] + d[6] + d[7]);
-        drho = (s - 0.5f * gx + uwx) / (1.0f - uwx);
-        rho = 1.0f + drho;
-        mx = rho * uwx - 0.5f * gx;
-        my = rho * uwy - 0.5f * gy;
-        d[1] = d[3] + (2.0f / 3.0f) * mx;
-        d[5] = d[7] - 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) + 0.5f * my;
-        d[8] = d[6] + 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) - 0.5f * my;
-    } else {
-        float s = d[0] + d[2] + d[4] + 2.0f * (d[1] + d[5] + d[8]);
-        drho = (s + 0.5f * gx - uwx) / (1.0f + uwx);
-        rho = 1.0f + drho;
-        mx = rho * uwx - 0.5f * gx;
-        my = rho * uwy - 0.5f * gy;
-        d[3] = d[1] - (2.0f / 3.0f) * mx;
-        d[7] = d[5] + 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) - 0.5f * my;
-        d[6] = d[8] - 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) + 0.5f * my;
-    }
-}
-
+// The Zou-He closures of walls_f64 written for deviations: the weights of
+// the known populations entering rho sum to 1, and w_i cancels in every
+// difference.  Same pass structure.
 __device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float d[9]) {
-    if (c.bcy == 1) {
-        if (y == 0) zouhe_dev(2, d, c.f_uw[2][0], c.f_uw[2][1], c.f_g[0], c.f_g[1]);
-        else if (y == c.ny - 1) zouhe_dev(3, d, c.f_uw[3][0], c.f_uw[3][1], c.f_g[0], c.f_g[1]);
+    const float gx = c.f_g[0], gy = c.f_g[1];
+    const bool s2 = c.bcy == 1 && y == 0;
+    const bool s3 = c.bcy == 1 && !s2 && y == c.ny - 1;
+    if (__any(s2 || s3)) {
+        float uwx = c.f_uw[2][0], uwy = c.f_uw[2][1];
+        float sm = d[0] + d[1] + d[3] + 2.0f * (d[4] + d[7] + d[8]);
+        float rho = 1.0f + (sm - 0.5f * gy + uwy) / (1.0f - uwy);
+        float mx = rho * uwx - 0.5f * gx;
+        float my = rho * uwy - 0.5f * gy;
+        const float a2 = d[4] + (2.0f / 3.0f) * my;
+        const float a5 = d[7] - 0.5f * (d[1] - d[3]) + 0.5f * mx + my * (1.0f / 6.0f);
+        const float a6 = d[8] + 0.5f * (d[1] - d[3]) - 0.5f * mx + my * (1.0f / 6.0f);
+        uwx = c.f_uw[3][0];
+        uwy = c.f_uw[3][1];
+        sm = d[0] + d[1] + d[3] + 2.0f * (d[2] + d[5] + d[6]);
+        rho = 1.0f + (sm + 0.5f * gy - uwy) / (1.0f + uwy);
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        const float b4 = d[2] - (2.0f / 3.0f) * my;
+        const float b7 = d[5] + 0.5f * (d[1] - d[3]) - 0.5f * mx - my * (1.0f / 6.0f);
+        const float b8 = d[6] - 0.5f * (d[1] - d[3]) + 0.5f * mx - my * (1.0f / 6.0f);
+        d[2] = s2 ? a2 : d[2];
+        d[5] = s2 ? a5 : d[5];
+        d[6] = s2 ? a6 : d[6];
+        d[4] = s3 ? b4 : d[4];
+        d[7] = s3 ? b7 : d[7];
+        d[8] = s3 ? b8 : d[8];
     }
-    if (c.bcx == 1) {
-        if (x == 0) zouhe_dev(0, d, c.f_uw[0][0], c.f_uw[0][1], c.f_g[0], c.f_g[1]);
-        else if (x == c.nx - 1) zouhe_dev(1, d, c.f_uw[1][0], c.f_uw[1][1], c.f_g[0], c.f_g[1]);
+    const bool s0 = c.bcx == 1 && x == 0;
+    const bool s1 = c.bcx == 1 && !s0 && x == c.nx - 1;
+    if (__any(s0 || s1)) {
+        float uwx = c.f_uw[0][0], uwy = c.f_uw[0][1];
+        float sm = d[0] + d[2] + d[4] + 2.0f * (d[3] + d[6] + d[7]);
+        float rho = 1.0f + (sm - 0.5f * gx + uwx) / (1.0f - uwx);
+        float mx = rho * uwx - 0.5f * gx;
+        float my = rho * uwy - 0.5f * gy;
+        const float a1 = d[3] + (2.0f / 3.0f) * mx;
+        const float a5 = d[7] - 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) + 0.5f * my;
+        const float a8 = d[6] + 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) - 0.5f * my;
+        uwx = c.f_uw[1][0];
+        uwy = c.f_uw[1][1];
+        sm = d[0] + d[2] + d[4] + 2.0f * (d[1] + d[5] + d[8]);
+        rho = 1.0f + (sm + 0.5f * gx - uwx) / (1.0f + uwx);
+        mx = rho * uwx - 0.5f * gx;
+        my = rho * uwy - 0.5f * gy;
+        const float b3 = d[1] - (2.0f / 3.0f) * mx;
+        const float b7 = d[5] + 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) - 0.5f * my;
+        const float b6 = d[8] - 0.5f * (d[2] - d[4]) - mx * (1.0f / 6.0f) + 0.5f * my;
+        d[1] = s0 ? a1 : d[1];
+        d[5] = s0 ? a5 : d[5];
+        d[8] = s0 ? a8 : d[8];
+        d[3] = s1 ? b3 : d[3];
+        d[7] = s1 ? b7 : d[7];
+        d[6] = s1 ? b6 : d[6];
     }
 }
 
@@ -314,6 +335,47 @@ __device__ __forceinline__ void patch_force_list(const StepArgs& a, const ChanDe
             fy += v.y;
         }
     }
+}
+
+// The same sum over a list held in registers (N fixed, n <= N used, all
+// indices compile-time so the list never goes to private memory).
+template <int N>
+__device__ __forceinline__ void patch_force_reg(const StepArgs& a, const ChanDev& c,
+                                                const int (&list)[N], int n, int x, int y,
+                                                double& fx, double& fy) {
+    fx = 0.0;
+    fy = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j >= n) break;
+        const PartDev& P = a.parts[list[j]];
+        int dx = x - P.bx0, dy = y - P.by0;
+        if (c.bcx == 0 && dx < 0) dx += c.nx;
+        if (c.bcy == 0 && dy < 0) dy += c.ny;
+        if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
+            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            fx += v.x;
+            fy += v.y;
+        }
+    }
+}
+
+// Inserts v into the ascending register list L[0, n) unless present.
+template <int N>
+__device__ __forceinline__ void list_insert(int (&L)[N], int& n, int v) {
+    bool dup = false;
+    int pos = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const bool in = m < n;
+        dup |= in && L[m] == v;
+        pos += (in && L[m] < v) ? 1 : 0;
+    }
+    if (dup || n >= N) return;
+#pragma unroll
+    for (int m = N - 1; m >= 1; --m) L[m] = m < pos ? L[m] : (m == pos ? v : L[m - 1]);
+    L[0] = pos == 0 ? v : L[0];
+    ++n;
 }
 
 // Do the boxes [x0, x0 + w) x [y0, y0 + h) and [u0, u0 + p) x [v0, v0 + q)
@@ -451,12 +513,12 @@ __device__ __forceinline__ MlsInv mls_inverse(const ChanDev& c, const double* w,
     return r;
 }
 
-// Append this particle to the lists of the lattice tiles that its patch box
+// Append particle pid to the lists of the lattice tiles that its patch box
 // [x0, x0 + w) x [y0, y0 + h) (unwrapped coordinates) overlaps, so the
 // lattice pass looks up particle forces only there and only for listed
 // particles.  Periodic ranges split into at most two pieces.
-__device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, int x0, int y0,
-                                           int w, int h, int tid, int nthr) {
+__device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, int pid, int x0,
+                                           int y0, int w, int h, int tid, int nthr) {
     int xr[2][2], yr[2][2], nxr = 0, nyr = 0;
     auto split = [](int lo, int len, int n, bool per, int r[2][2]) {
         int cnt = 0;
@@ -485,7 +547,7 @@ __device__ __forceinline__ void mark_tiles(const StepArgs& a, const ChanDev& c, 
             for (int t = tid; t < cnt; t += nthr) {
                 int* e = tl + (long long)(c.tile0 + (ty0 + t / ntx) * c.tiles_x + tx0 + t % ntx) * kTileList;
                 const int slot = atomicAdd(e, 1);
-                if (slot < kTileList - 1) e[1 + slot] = (int)blockIdx.x;
+                if (slot < kTileList - 1) e[1 + slot] = pid;
             }
         }
 }

@@ -6,9 +6,8 @@
 
 namespace lbmk {
 
-constexpr int kMaxCellsDefault = 8192;   // force-patch cells of one particle (raised from
-                                         // the device's LDS size at init)
-constexpr int kChunk = 32;               // markers per spreading chunk (one u32 mask)
+constexpr int kMaxCells = 32768;         // force-patch cells of one particle
+constexpr int kMaxMarkers = 1024;        // markers of one particle
 constexpr int kRecSlots = 1024;          // trajectory ring-buffer depth (steps)
 constexpr int kMaxNeighbours = 8;        // short candidate lists of force patches
 constexpr int kTileList = 8;             // per-tile list: count + 7 particle indices
@@ -52,6 +51,7 @@ struct PartDev {
     int chan, mbeg, nm, patch_cap;
     int bx0, by0, bw, bh;    // patch box in unwrapped lattice coordinates
     long long patch_off;     // first cell of the patch in the patch pool
+    long long part_off;      // first cell of the per-round partial patches (several rounds)
 };
 
 struct StepArgs {
@@ -69,16 +69,23 @@ struct StepArgs {
     const double2* nrm;
     const double* ds;
     double2* patch;          // force patches
-    double2* contrib;        // [markers][9] spread contributions
-    double* mscr;            // [markers][4] traction scratch
+    double* mscr;            // [markers][4] traction terms (particles of several rounds)
     int* flags;              // [0] unstable, [1] first bad step, [2] capacity
     long long* dstep;        // steps started so far
     double* rec;             // [kRecSlots][nparts][10]
-    int max_cells;           // LDS mask capacity of the spreading kernel
+    int max_cells;           // force-patch cells of one particle
     int* tlist;              // [2][ntiles][kTileList] particles whose patches touch a tile
     int parity;              // which half of tlist this step fills / reads
     int tile_w, tile_h;      // tile extent in nodes
     PartDev* snap;           // optional: copy of each particle after the force stage
+    const int2* work;        // [nwork] particle-kernel workgroups: (particle, round of
+                             // kRound markers), particle-major
+    int nwork;
+    int* pcount;             // [nparts] finished surface-stress workgroups; 0 between launches
+    double2* partial;        // per-round partial force patches of particles of several rounds
+    const int2* psum;        // [npsum] (particle, first cell) chunks of 256 patch cells of
+                             // particles of several rounds
+    int npsum;
 };
 
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
@@ -89,6 +96,9 @@ hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx,
 hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s);
 hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hipStream_t s);
 hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s);
+// Force patches of particles of several rounds from their partial patches
+// (after launch_ibm_force).
+hipError_t launch_patch_sum(const StepArgs& a, hipStream_t s);
 // Lattice pass and surface stress in one launch (tile_w 64, tile_h 9 * npt,
 // no persistent workgroups).
 hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, hipStream_t s);
@@ -96,8 +106,6 @@ hipError_t launch_fields(int store, const StepArgs& a, int chan, int nx, int ny,
                          double* rho, double* ux, double* uy, hipStream_t s);
 hipError_t launch_set_pop(int store, const StepArgs& a, int chan, int nx, int ny,
                           const double* f_in, hipStream_t s);
-size_t ibm_lds_bytes(int max_cells);
-size_t ibm_static_lds_bytes();
 
 // Adjoint state of one particle (adjoint of its step-n state, accumulated
 // shape and mass gradients) and its adjoint patch, which covers the stencils

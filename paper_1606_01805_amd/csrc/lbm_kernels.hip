@@ -29,27 +29,135 @@
 namespace lbmk {
 
 // ---------------------------------------------------------------------------
-// Kernel 1: immersed-boundary force and spreading (one workgroup / particle).
+// Cross-workgroup completion of a particle whose markers span several
+// workgroups (one per round of 64 markers).  Every workgroup publishes its
+// per-marker results to global scratch, then counts itself done; the one that
+// counts last finishes the particle from the published results.
 //
-// Markers are processed in rounds of 64 by 576 threads, one per (marker,
-// stencil node) pair: each pair thread evaluates one MLS weight and pulls the
-// moments of one stencil node; the k = 0 thread of each marker then assembles
-// the 3x3 moment matrix and interpolant in ascending node order, exactly as
-// the reference formulation does, and leaves the marker's contributions
-// c_l phi_k F_l in LDS for the spreading of the same round.
+// Each XCD has its own L2, so data that crosses workgroups inside a launch
+// is stored and loaded with relaxed device-scope atomics, which the compiler
+// emits as accesses coherent across the L2s.  Ordering against the counter
+// comes from waiting for the stores to complete before counting, and from
+// loading only after the counter has been read (workgroup-scope fences keep
+// the compiler from moving accesses across).  The counter is reset by the
+// finisher, so it reads zero at every launch boundary.  No workgroup ever
+// waits for another, and the finishing arithmetic runs in a fixed order, so
+// the result does not depend on which workgroup finishes.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void pub_store(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double pub_load(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// s_waitcnt with vmcnt = 0 (expcnt, lgkmcnt left at their maxima): every
+// vector memory access of the thread has completed.
+constexpr int kWaitVmem = 0 | (0x7 << 4) | (0xf << 8);
+
+__device__ __forceinline__ bool finish_last(int* counter, int n) {
+    __shared__ int s_last;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(counter, 1) == n - 1;
+    __syncthreads();
+    const bool last = s_last != 0;
+    if (last && threadIdx.x == 0) *counter = 0;
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return last;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: immersed-boundary force and spreading (each workgroup takes a
+// range of rounds of 64 markers of one particle).
+//
+// Each round runs 576 threads, one per (marker, stencil node) pair: each pair
+// thread evaluates one MLS weight and pulls the moments of one stencil node;
+// the k = 0 thread of each marker then assembles the 3x3 moment matrix and
+// interpolant in ascending node order, exactly as the reference formulation
+// does, and leaves the marker's contributions c_l phi_k F_l in LDS, and the
+// round spreads them.  A particle of one round spreads into its force patch
+// directly.  A particle of several rounds spreads each round into a partial
+// patch of its own, and the next kernel adds the partial patches cell by
+// cell in ascending round order.  Every node thus sums its terms in a fixed
+// order: ascending markers within a round, then ascending rounds.
+// ---------------------------------------------------------------------------
+
+// Spreading f_lb(x_k) = sum_l c_l phi^l_k F_l.  The contributions of the
+// round's markers are in s_con and their stencil anchors in s_anc.  The
+// markers are spread in consecutive groups [g0, g1): a group's anchor masks
+// (one bit per marker of the round) live on the bounding box of its anchors,
+// [gx0, gx0 + gw) x [gy0, gy0 + gh) in unwrapped lattice coordinates, which
+// must fit kMaskCells.  The lowest marker of the group covering a node owns
+// it and adds the group's terms in ascending marker order onto the value the
+// earlier groups left (the first group starts from zero), so each node sums
+// the round's terms in ascending marker order, with no float atomics.
+constexpr int kMaskCells = 4096;
+
+__device__ __forceinline__ void spread_group(const ChanDev& c, const unsigned long long* gmask,
+                                            const double2* s_con, const int2* s_anc, double2* target,
+                                            int bx0u, int by0u, int bw, int gx0, int gy0, int gw,
+                                            int gh, int lo, int k, bool mine, bool first) {
+    if (!mine) return;
+    const int2 an = s_anc[lo];
+    const int ni = an.x + k % 3 - 1, nj = an.y + k / 3 - 1;
+    if (!node_valid(c, ni, nj)) return;
+    unsigned long long msk = 0ull;
+    for (int db = -1; db <= 1; ++db) {
+        const int cy = nj + db - gy0;
+        if (cy < 0 || cy >= gh) continue;
+        for (int da = -1; da <= 1; ++da) {
+            const int cx = ni + da - gx0;
+            if (cx < 0 || cx >= gw) continue;
+            msk |= gmask[cy * gw + cx];
+        }
+    }
+    if (msk & ((1ull << lo) - 1ull)) return;
+    const int cell = (nj - by0u) * bw + (ni - bx0u);
+    double2 acc = make_double2(0.0, 0.0);
+    if (!first) acc = target[cell];
+    while (msk) {
+        const int b = __ffsll((long long)msk) - 1;
+        msk &= msk - 1ull;
+        const int2 a2 = s_anc[b];
+        const int k2 = 3 * (nj - a2.y + 1) + (ni - a2.x + 1);
+        const double2 v = s_con[b * 9 + k2];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    target[cell] = acc;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
 template <int ST>
 __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
-    extern __shared__ unsigned long long smask[];  // [max_cells] markers anchored per cell
+    __shared__ unsigned long long gmask[kMaskCells];  // anchor masks of the group being spread
     __shared__ double s_w[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
-    __shared__ double2 s_con[kIbmThreads];         // c_l phi_k F_l of the round
+    __shared__ double2 s_con[kIbmThreads];            // c_l phi_k F_l of the round
     __shared__ int2 s_anc[kRound];
+    __shared__ int s_grp[5];                           // g1, gx0, gy0, gw, gh
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
-    if ((int)blockIdx.x >= a.nparts) return;
-    PartDev* P = a.parts + blockIdx.x;
+    if ((int)blockIdx.x >= a.nwork) return;
+    const int2 wk = a.work[blockIdx.x];
+    const int pid = wk.x;
+    PartDev* P = a.parts + pid;
     const ChanDev& c = a.chan[P->chan];
     const int nm = P->nm, mb = P->mbeg;
+    const int nr = (nm + kRound - 1) / kRound, r0 = wk.y * kRound;
+    const bool lead = wk.y == 0;  // the round-0 workgroup owns the particle's bookkeeping
     const double X0 = P->X[0], X1 = P->X[1], th = P->th;
     const double V0 = P->V[0], V1 = P->V[1], Om = P->Om;
     // A particle whose state is no longer finite, or far outside any
@@ -57,12 +165,12 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     // meaningless and must never index memory.
     const double lim = 1e8;
     if (!(fabs(X0) < lim) || !(fabs(X1) < lim) || !(fabs(th) < lim)) {
-        if (tid == 0) {
+        if (lead && tid == 0) {
             P->bw = 0;
             P->bh = 0;
             a.flags[0] = 1;
             atomicMin(&a.flags[1], (int)(*a.dstep - 1));
-            if (a.snap) a.snap[blockIdx.x] = *P;
+            if (a.snap) a.snap[pid] = *P;
         }
         return;
     }
@@ -70,131 +178,181 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     // within rb of the centroid (anchors round half up, plus one node).
     int bx0u, by0u, bw, bh;
     stencil_box(X0, X1, P->rb, bx0u, by0u, bw, bh);
-    if (bw > c.nx || bh > c.ny || (long long)bw * bh > P->patch_cap || (long long)bw * bh > a.max_cells) {
-        if (tid == 0) {
+    if (bw > c.nx || bh > c.ny || (long long)bw * bh > P->patch_cap) {
+        if (lead && tid == 0) {
             atomicOr(&a.flags[2], 1);
             P->bw = 0;
             P->bh = 0;
-            if (a.snap) a.snap[blockIdx.x] = *P;
+            if (a.snap) a.snap[pid] = *P;
         }
         return;
     }
     const int ncell = bw * bh;
     double2* patch = a.patch + P->patch_off;
-    for (int k = tid; k < ncell; k += blockDim.x) smask[k] = 0ull;
-    if (tid == 0) {
+    // nr partial patches of patch_cap cells (nr > 1)
+    double2* target = nr == 1 ? patch : a.partial + P->part_off + (long long)wk.y * P->patch_cap;
+    for (int q = tid; q < kMaskCells; q += blockDim.x) gmask[q] = 0ull;
+    if (lead && tid == 0) {
         P->bx0 = wrapc(bx0u, c.nx, c.bcx == 0);
         P->by0 = wrapc(by0u, c.ny, c.bcy == 0);
         P->bw = bw;
         P->bh = bh;
-        if (a.snap) a.snap[blockIdx.x] = *P;
+        if (a.snap) a.snap[pid] = *P;
     }
     const double cs = cos(th), sn = sin(th);
 
     const int lo = tid / 9, k = tid % 9;
-    for (int r0 = 0; r0 < nm; r0 += kRound) {
-        const int l = r0 + lo;
-        const bool act = l < nm;
-        // (1) one weight and the force-free velocity u* = j*/rho of one node
-        if (act) {
-            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
-            double dx, dy;
-            int ni, nj;
-            double w = 0.0, ux = 0.0, uy = 0.0;
-            if (stencil_node(c, m.i0, m.j0, k, m.xl, m.yl, dx, dy, ni, nj)) {
-                w = stencil_weight(c, dx, dy);
-                double f[9], rho, jx, jy;
-                pull_node_f64<ST>(a.fin, c, ni, nj, f);
-                moments_f64(f, c, rho, jx, jy);
-                ux = jx / rho;
-                uy = jy / rho;
-            }
-            s_w[tid] = w;
-            s_ux[tid] = ux;
-            s_uy[tid] = uy;
-            if (k == 0) s_anc[lo] = make_int2(m.i0, m.j0);
+    const int l = r0 + lo;
+    const bool act = l < nm;
+    const int nact = nm - r0 < kRound ? nm - r0 : kRound;  // markers of this round
+    // (1) one weight and the force-free velocity u* = j*/rho of one node
+    if (act) {
+        const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+        double dx, dy;
+        int ni, nj;
+        double w = 0.0, ux = 0.0, uy = 0.0;
+        if (stencil_node(c, m.i0, m.j0, k, m.xl, m.yl, dx, dy, ni, nj)) {
+            w = stencil_weight(c, dx, dy);
+            double f[9], rho, jx, jy;
+            pull_node_f64<ST>(a.fin, c, ni, nj, f);
+            moments_f64(f, c, rho, jx, jy);
+            ux = jx / rho;
+            uy = jy / rho;
         }
-        __syncthreads();
-        if (tid < kRound) {
-            // (2) per marker, all in the first wave (thread lo leads marker
-            // r0 + lo): phi, U = sum phi u* (k ascending), F = U_b - U
-            // (dt = 1), contributions; its bit in the mask of its anchor cell
-            if (r0 + tid < nm) {
-                const int lo = tid, l = r0 + lo;
-                const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
-                const double cl = c.spread_unit ? 1.0 : a.ds[mb + l];
-                const double* w = s_w + lo * 9;
-                const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, false);
-                double Ux = 0.0, Uy = 0.0;
-                for (int q = 0; q < 9; ++q) {
-                    const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                    if (!node_valid(c, ii, jj)) continue;
+        s_w[tid] = w;
+        s_ux[tid] = ux;
+        s_uy[tid] = uy;
+        if (k == 0) s_anc[lo] = make_int2(m.i0, m.j0);
+    }
+    __syncthreads();
+    if (tid < kRound) {
+        // (2) per marker, all in the first wave (thread lo leads marker
+        // r0 + lo): phi, U = sum phi u* (k ascending), F = U_b - U (dt = 1)
+        // and the contributions
+        if (r0 + tid < nm) {
+            const int lo = tid, l = r0 + lo;
+            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+            const double cl = c.spread_unit ? 1.0 : a.ds[mb + l];
+            const double* w = s_w + lo * 9;
+            const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, false);
+            double Ux = 0.0, Uy = 0.0;
+            for (int q = 0; q < 9; ++q) {
+                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
+                if (!node_valid(c, ii, jj)) continue;
+                const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
+                const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
+                Ux += phi * s_ux[lo * 9 + q];
+                Uy += phi * s_uy[lo * 9 + q];
+            }
+            const double ubx = V0 - Om * m.ry;
+            const double uby = V1 + Om * m.rx;
+            const double Fx = ubx - Ux, Fy = uby - Uy;
+            for (int q = 0; q < 9; ++q) {
+                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
+                double2 v = make_double2(0.0, 0.0);
+                if (node_valid(c, ii, jj)) {
                     const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
                     const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
-                    Ux += phi * s_ux[lo * 9 + q];
-                    Uy += phi * s_uy[lo * 9 + q];
+                    v = make_double2(cl * phi * Fx, cl * phi * Fy);
                 }
-                const double ubx = V0 - Om * m.ry;
-                const double uby = V1 + Om * m.rx;
-                const double Fx = ubx - Ux, Fy = uby - Uy;
-                for (int q = 0; q < 9; ++q) {
-                    const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                    double2 v = make_double2(0.0, 0.0);
-                    if (node_valid(c, ii, jj)) {
-                        const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
-                        const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
-                        v = make_double2(cl * phi * Fx, cl * phi * Fy);
-                    }
-                    s_con[lo * 9 + q] = v;
-                }
-                atomicOr(&smask[(m.j0 - by0u) * bw + (m.i0 - bx0u)], 1ull << lo);
-            }
-        } else if (r0 == 0) {
-            // meanwhile the other waves clear the patch and list the tiles it
-            // covers for the lattice pass
-            for (int q = tid - kRound; q < ncell; q += blockDim.x - kRound) patch[q] = make_double2(0.0, 0.0);
-            mark_tiles(a, c, bx0u, by0u, bw, bh, tid - kRound, blockDim.x - kRound);
-        }
-        __syncthreads();
-        // (3) spreading f_lb(x_k) = sum_l c_l phi^l_k F_l: the lowest marker
-        // of the round covering a node owns it and adds the round's terms in
-        // ascending marker order onto the sums of the earlier rounds, so each
-        // node receives its terms in ascending marker order, with no float
-        // atomics.
-        if (act) {
-            const int2 an = s_anc[lo];
-            const int ni = an.x + k % 3 - 1, nj = an.y + k / 3 - 1;
-            if (node_valid(c, ni, nj)) {
-                unsigned long long msk = 0ull;
-                for (int db = -1; db <= 1; ++db) {
-                    const int cy = nj + db - by0u;
-                    if (cy < 0 || cy >= bh) continue;
-                    for (int da = -1; da <= 1; ++da) {
-                        const int cx = ni + da - bx0u;
-                        if (cx < 0 || cx >= bw) continue;
-                        msk |= smask[cy * bw + cx];
-                    }
-                }
-                if (!(msk & ((1ull << lo) - 1ull))) {
-                    const int cell = (nj - by0u) * bw + (ni - bx0u);
-                    double2 acc = r0 == 0 ? make_double2(0.0, 0.0) : patch[cell];
-                    while (msk) {
-                        const int b = __ffsll((long long)msk) - 1;
-                        msk &= msk - 1ull;
-                        const int2 a2 = s_anc[b];
-                        const int k2 = 3 * (nj - a2.y + 1) + (ni - a2.x + 1);
-                        const double2 v = s_con[b * 9 + k2];
-                        acc.x += v.x;
-                        acc.y += v.y;
-                    }
-                    patch[cell] = acc;
-                }
+                s_con[lo * 9 + q] = v;
             }
         }
-        __syncthreads();
-        if (act && k == 0) smask[(s_anc[lo].y - by0u) * bw + (s_anc[lo].x - bx0u)] = 0ull;
-        __syncthreads();
+        // the anchor box of the whole round; when it fits the masks, they
+        // are set here and the round spreads as one group
+        const bool in = tid < nact;
+        const int2 an = s_anc[in ? tid : 0];
+        const int x0 = wave_min(in ? an.x : INT_MAX), y0 = wave_min(in ? an.y : INT_MAX);
+        const int x1 = wave_max(in ? an.x : INT_MIN), y1 = wave_max(in ? an.y : INT_MIN);
+        const bool fits = (long long)(x1 - x0 + 1) * (y1 - y0 + 1) <= kMaskCells;
+        if (fits && in) atomicOr(&gmask[(an.y - y0) * (x1 - x0 + 1) + (an.x - x0)], 1ull << tid);
+        if (tid == 0) {
+            s_grp[0] = fits ? nact : 0;
+            s_grp[1] = x0;
+            s_grp[2] = y0;
+            s_grp[3] = x1 - x0 + 1;
+            s_grp[4] = y1 - y0 + 1;
+        }
+    } else {
+        // meanwhile the other waves clear the round's target (the patch, or
+        // the round's partial patch) and the lead lists the tiles the patch
+        // covers for the lattice pass
+        for (int q = tid - kRound; q < ncell; q += blockDim.x - kRound) target[q] = make_double2(0.0, 0.0);
+        if (lead) mark_tiles(a, c, pid, bx0u, by0u, bw, bh, tid - kRound, blockDim.x - kRound);
     }
+    __syncthreads();
+    // (3) spreading: the whole round as one group, or else in groups of
+    // markers whose anchor box fits the masks
+    if (s_grp[0] == nact) {
+        spread_group(c, gmask, s_con, s_anc, target, bx0u, by0u, bw, s_grp[1], s_grp[2], s_grp[3],
+                     s_grp[4], lo, k, act, true);
+        return;
+    }
+    __syncthreads();  // every thread has read s_grp before the groups rewrite it
+    for (int g0 = 0; g0 < nact;) {
+        if (tid < 64) {
+            // the first wave picks the largest group [g0, g0 + n), n halving
+            // from all remaining markers, whose anchor box fits
+            int n = nact - g0, x0, y0, x1, y1;
+            for (;;) {
+                const bool in = tid >= g0 && tid < g0 + n;
+                const int2 an = s_anc[tid < nact ? tid : 0];
+                x0 = wave_min(in ? an.x : INT_MAX);
+                y0 = wave_min(in ? an.y : INT_MAX);
+                x1 = wave_max(in ? an.x : INT_MIN);
+                y1 = wave_max(in ? an.y : INT_MIN);
+                if (n == 1 || (long long)(x1 - x0 + 1) * (y1 - y0 + 1) <= kMaskCells) break;
+                n = (n + 1) / 2;
+            }
+            if (tid == 0) {
+                s_grp[0] = g0 + n;
+                s_grp[1] = x0;
+                s_grp[2] = y0;
+                s_grp[3] = x1 - x0 + 1;
+                s_grp[4] = y1 - y0 + 1;
+            }
+        }
+        __syncthreads();
+        const int g1 = s_grp[0], gx0 = s_grp[1], gy0 = s_grp[2], gw = s_grp[3], gh = s_grp[4];
+        if (tid >= g0 && tid < g1)
+            atomicOr(&gmask[(s_anc[tid].y - gy0) * gw + (s_anc[tid].x - gx0)], 1ull << tid);
+        __syncthreads();
+        spread_group(c, gmask, s_con, s_anc, target, bx0u, by0u, bw, gx0, gy0, gw, gh, lo, k,
+                     act && lo >= g0 && lo < g1, g0 == 0);
+        if (g1 == nact) break;
+        // another group follows: it may read the cells just written, and the
+        // masks are cleared for it
+        __syncthreads();
+        if (tid >= g0 && tid < g1) gmask[(s_anc[tid].y - gy0) * gw + (s_anc[tid].x - gx0)] = 0ull;
+        __syncthreads();
+        g0 = g1;
+    }
+}
+
+// Force patches of particles of several rounds: the sum of the partial
+// patches in ascending round order (the first round starts the sum), one
+// thread per patch cell; workgroups take (particle, 256-cell chunk) pairs.
+__global__ __launch_bounds__(256) void patch_sum_kernel(StepArgs a) {
+    if ((int)blockIdx.x >= a.npsum) return;
+    const int2 e = a.psum[blockIdx.x];
+    const PartDev& P = a.parts[e.x];
+    const int q = e.y + (int)threadIdx.x;
+    if (q >= P.bw * P.bh) return;  // bw = 0 for a particle the force stage skipped
+    const int nr = (P.nm + kRound - 1) / kRound;
+    const double2* part = a.partial + P.part_off + q;
+    const long long cap = P.patch_cap;
+    constexpr int kMaxRounds = (kMaxMarkers + kRound - 1) / kRound;
+    double2 v[kMaxRounds];
+#pragma unroll
+    for (int r = 0; r < kMaxRounds; ++r) v[r] = r < nr ? part[r * cap] : make_double2(0.0, 0.0);
+    double2 acc = v[0];
+#pragma unroll
+    for (int r = 1; r < kMaxRounds; ++r)
+        if (r < nr) {
+            acc.x += v[r].x;
+            acc.y += v[r].y;
+        }
+    a.patch[P.patch_off + q] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -202,14 +360,14 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
 // ---------------------------------------------------------------------------
 // FP64 form, reference expression order.  f holds the pulled populations.
 __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c, int x,
-                                                  int y, double f[9], const int* list, int nlist,
+                                                  int y, double f[9], const int (&list)[kTileList - 1], int nlist,
                                                   double* __restrict__ fout) {
     walls_f64(c, x, y, f);
     double rho, jx, jy;
     moments_f64(f, c, rho, jx, jy);
     double flbx = 0.0, flby = 0.0;
     if (nlist >= kTileList) patch_force(a, c, x, y, flbx, flby);
-    else if (nlist > 0) patch_force_list(a, c, list, nlist, x, y, flbx, flby);
+    else if (nlist > 0) patch_force_reg(a, c, list, nlist, x, y, flbx, flby);
     const double gx = c.g[0], gy = c.g[1];
     const double ux = (jx + 0.5 * flbx) / rho;
     const double uy = (jy + 0.5 * flby) / rho;
@@ -236,7 +394,7 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
 // Reduced forms: deviations in FP32.  d holds the pulled deviations.
 template <int ST>
 __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c, int x,
-                                                  int y, float d[9], const int* list, int nlist,
+                                                  int y, float d[9], const int (&list)[kTileList - 1], int nlist,
                                                   typename Sto<ST>::T* __restrict__ fout) {
     walls_dev(c, x, y, d);
     const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
@@ -245,7 +403,7 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
     if (nlist > 0) {
         double fx, fy;
         if (nlist >= kTileList) patch_force(a, c, x, y, fx, fy);
-        else patch_force_list(a, c, list, nlist, x, y, fx, fy);
+        else patch_force_reg(a, c, list, nlist, x, y, fx, fy);
         flbx = (float)fx;
         flby = (float)fy;
     }
@@ -293,24 +451,12 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
     const int* e = tl_cur + (long long)t * kTileList;
     const int cnt = uni(e[0]);
     if (threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
-    int list[kTileList - 1];
+    int list[kTileList - 1] = {};
     int nlist = 0;
     if (cnt > kTileList - 1) {
         nlist = kTileList;  // more patches than slots: scan the channel's particles
     } else {
-        for (int j = 0; j < cnt; ++j) {
-            const int v = uni(e[1 + j]);
-            int k = nlist;
-            bool dup = false;
-            for (int m = 0; m < nlist; ++m) dup |= list[m] == v;
-            if (dup) continue;
-            while (k > 0 && list[k - 1] > v) {
-                list[k] = list[k - 1];
-                --k;
-            }
-            list[k] = v;
-            ++nlist;
-        }
+        for (int j = 0; j < cnt; ++j) list_insert(list, nlist, uni(e[1 + j]));
     }
     // all pulls of the thread's rows first, then collide and store
     if constexpr (ST == ST_F64) {
@@ -368,15 +514,16 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 3: surface stress, force, moment and BDF2 (one workgroup / particle).
-// Pair threads (marker, probe-stencil node) evaluate one weight and the
-// corrected fields of one node; the k = 0 thread of each marker builds the
-// probe's MLS value and gradient weights and the marker's traction.
+// Kernel 3: surface stress, force, moment and BDF2 (one workgroup per round
+// of 64 markers of a particle).  Pair threads (marker, probe-stencil node)
+// evaluate one weight and the corrected fields of one node; the k = 0 thread
+// of each marker builds the probe's MLS value and gradient weights and the
+// marker's traction.
 // ---------------------------------------------------------------------------
 template <int ST>
-__device__ __forceinline__ void traction_body(const StepArgs& a, int b) {
+__device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd) {
     __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
-    __shared__ double s_t[3][1024];
+    __shared__ double s_t[3][kRound];
     __shared__ double sums[3];
     const int tid = threadIdx.x;
     PartDev* P = a.parts + b;
@@ -386,6 +533,12 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b) {
     const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
     const double nu = c.nu, dn = c.dn;
     const bool skip = P->bw <= 0;  // flagged by the force stage
+    // One workgroup per round of 64 markers; a particle of several rounds
+    // publishes the per-marker terms and its last workgroup sums them.  A
+    // skipped particle is finished by its round-0 workgroup alone.
+    if (skip && rnd > 0) return;
+    const int nr = (nm + kRound - 1) / kRound;
+    const bool multi = nr > 1 && !skip;
     const double cs = skip ? 1.0 : cos(th), sn = skip ? 0.0 : sin(th);
     const int lo = tid / 9, k = tid % 9;
     // Particles of the channel whose force patches can reach this particle's
@@ -417,7 +570,8 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b) {
     __syncthreads();
     const int nnb = s_nnb;
 
-    for (int r0 = 0; r0 < (skip ? 0 : nm); r0 += kRound) {
+    if (!skip) {
+        const int r0 = rnd * kRound;
         const int l = r0 + lo;
         const bool act = l < nm;
         if (act) {
@@ -491,19 +645,41 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b) {
             const double tx = txx * nxl + txy * nyl - pl * nxl;
             const double ty = txy * nxl + tyy * nyl - pl * nyl;
             const double S = a.ds[mb + l];
-            s_t[0][l] = tx * S;
-            s_t[1][l] = ty * S;
-            s_t[2][l] = (rx * ty - ry * tx) * S;
+            const double t0 = tx * S, t1 = ty * S, t2 = (rx * ty - ry * tx) * S;
+            if (multi) {
+                double* o = a.mscr + (long long)(mb + l) * 4;
+                pub_store(o, t0);
+                pub_store(o + 1, t1);
+                pub_store(o + 2, t2);
+            } else {
+                s_t[0][lm] = t0;
+                s_t[1][lm] = t1;
+                s_t[2][lm] = t2;
+            }
         }
         __syncthreads();
     }
-    // Force and moment: sums over the markers in ascending order.
-    if (tid < 3) {
-        double s = 0.0;
-        if (!skip)
-            for (int l = 0; l < nm; ++l) s += s_t[tid][l];
-        sums[tid] = s;
+    if (multi && !finish_last(a.pcount + b, nr)) return;
+    // Force and moment: sums over the markers in ascending order (thread
+    // tid < 3 sums component tid).  Published terms are staged through LDS
+    // 192 markers at a time, every thread loading one term.
+    double fsum = 0.0;
+    if (multi) {
+        constexpr int kStage = kIbmThreads / 3;
+        for (int base = 0; base < nm; base += kStage) {
+            const int l = base + tid / 3;
+            s_w[tid] = l < nm ? pub_load(a.mscr + (long long)(mb + l) * 4 + tid % 3) : 0.0;
+            __syncthreads();
+            if (tid < 3) {
+                const int n = nm - base < kStage ? nm - base : kStage;
+                for (int j = 0; j < n; ++j) fsum += s_w[3 * j + tid];
+            }
+            __syncthreads();
+        }
+    } else if (!skip && tid < 3) {
+        for (int l = 0; l < nm; ++l) fsum += s_t[tid][l];
     }
+    if (tid < 3) sums[tid] = fsum;
     __syncthreads();
     if (tid != 0) return;
     const double Fx = sums[0], Fy = sums[1], Mz = sums[2];
@@ -557,21 +733,28 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b) {
 
 template <int ST>
 __global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
-    if ((int)blockIdx.x < a.nparts) traction_body<ST>(a, (int)blockIdx.x);
+    if ((int)blockIdx.x < a.nwork) {
+        const int2 wk = a.work[blockIdx.x];
+        traction_body<ST>(a, wk.x, wk.y);
+    }
 }
 
 // The surface stress of step n reads the populations entering the step and
 // the force patches of the step, the lattice pass reads the same and writes
 // only the populations leaving it, so the two share one launch: workgroups
-// [0, tb) take the particles (tb = nparts rounded up to a multiple of 8, so
-// that lattice workgroup j lands on XCD j mod 8 as in the lattice kernel)
-// and the rest take lattice tiles of 64 x 9*NPT nodes.  The particle
-// workgroups are dispatched first and run alongside the lattice tiles.
+// [0, tb) take the particles' marker rounds (tb = the number of rounds
+// rounded up to a multiple of 8, so that lattice workgroup j lands on XCD
+// j mod 8 as in the lattice kernel) and the rest take lattice tiles of
+// 64 x 9*NPT nodes.  The particle workgroups are dispatched first and run
+// alongside the lattice tiles.
 template <int ST, int NPT>
 __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs a, int tb) {
     const int j = (int)blockIdx.x - tb;
     if (j < 0) {
-        if ((int)blockIdx.x < a.nparts) traction_body<ST>(a, (int)blockIdx.x);
+        if ((int)blockIdx.x < a.nwork) {
+            const int2 wk = a.work[blockIdx.x];
+            traction_body<ST>(a, wk.x, wk.y);
+        }
         return;
     }
     int t = j;
@@ -673,7 +856,6 @@ __global__ void set_pop_kernel(StepArgs a, int chan, const double* fi) {
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-size_t ibm_lds_bytes(int max_cells) { return sizeof(unsigned long long) * max_cells; }
 
 #define LBM_DISPATCH(store, F)                     \
     switch (store) {                               \
@@ -697,27 +879,9 @@ hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx,
 }
 
 // Static LDS of the force kernel, as compiled (the mask store takes the rest).
-size_t ibm_static_lds_bytes() {
-    size_t m = 3 * sizeof(double) * kIbmThreads + sizeof(double2) * kIbmThreads + sizeof(int2) * kRound + 64;
-    hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, (const void*)ibm_force_kernel<ST_F64>) == hipSuccess) m = std::max(m, fa.sharedSizeBytes);
-    if (hipFuncGetAttributes(&fa, (const void*)ibm_force_kernel<ST_F32>) == hipSuccess) m = std::max(m, fa.sharedSizeBytes);
-    if (hipFuncGetAttributes(&fa, (const void*)ibm_force_kernel<ST_F16S>) == hipSuccess) m = std::max(m, fa.sharedSizeBytes);
-    return m;
-}
-
 hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s) {
-    const int grid = a.nparts > 0 ? a.nparts : 1;
-    const size_t lds = ibm_lds_bytes(a.max_cells);
-    if (lds > 65536) {
-        hipError_t e = hipSuccess;
-#define A_(ST) e = hipFuncSetAttribute((const void*)ibm_force_kernel<ST>, \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-        LBM_DISPATCH(store, A_)
-#undef A_
-        if (e != hipSuccess) return e;
-    }
-#define L_(ST) ibm_force_kernel<ST><<<grid, kIbmThreads, lds, s>>>(a)
+    const int grid = a.nwork > 0 ? a.nwork : 1;  // workgroup 0 also counts the step
+#define L_(ST) ibm_force_kernel<ST><<<grid, kIbmThreads, 0, s>>>(a)
     LBM_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();
@@ -755,9 +919,15 @@ hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hip
     }
 }
 
+hipError_t launch_patch_sum(const StepArgs& a, hipStream_t s) {
+    if (a.npsum <= 0) return hipSuccess;
+    patch_sum_kernel<<<a.npsum, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s) {
-    if (a.nparts <= 0) return hipSuccess;
-#define L_(ST) traction_kernel<ST><<<a.nparts, kIbmThreads, 0, s>>>(a)
+    if (a.nwork <= 0) return hipSuccess;
+#define L_(ST) traction_kernel<ST><<<a.nwork, kIbmThreads, 0, s>>>(a)
     LBM_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();
@@ -774,7 +944,7 @@ static hipError_t lattice_traction_dispatch(const StepArgs& a, int npt, int tb, 
 
 hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, hipStream_t s) {
     if (a.persistent > 0 || a.tile_w != 64 || a.tile_h != 9 * npt) return hipErrorInvalidValue;
-    const long long tb = a.nparts > 0 ? ((long long)a.nparts + 7) / 8 * 8 : 0;
+    const long long tb = a.nwork > 0 ? ((long long)a.nwork + 7) / 8 * 8 : 0;
     const long long tl = a.xcd_remap ? ((long long)a.ntiles + 7) / 8 * 8 : a.ntiles;
     const long long grid = tb + tl;
     if (grid <= 0) return hipSuccess;

@@ -61,6 +61,43 @@ def test_batched_fp64_matches_oracle():
         pid += 1
 
 
+def _multi_round_channels(storage):
+    """Particles of 2 to 4 rounds of 64 markers (dense circles and ellipses),
+    one or two per channel, so the particle kernels run several workgroups
+    per particle and workgroup and particle indices differ."""
+    chans = []
+    specs = [(48, [(shapes.circle(12.0, n_markers=150), 40.3, 23.6, 0.0)]),
+             (40, [(shapes.ellipse(14.0, 2.0, n_markers=70), 25.2, 19.1, 0.6),
+                   (shapes.circle(10.0, n_markers=201), 90.7, 20.4, 0.0)]),
+             (36, [(shapes.circle(8.0, n_markers=64), 60.0, 17.2, 0.0)]),
+             (44, [(shapes.ellipse(16.0, 2.5, n_markers=256), 100.5, 22.3, 1.1)])]
+    for k, (H, ps) in enumerate(specs):
+        cfg = C.couette_config(4 * H + 3 * k, H, storage=storage)
+        chans.append((cfg, [C.particle(sh, x, y, th) for sh, x, y, th in ps]))
+    return chans
+
+
+@pytest.mark.parametrize("storage", [C.STORE_F32, C.STORE_F64])
+def test_batched_multi_round_particles(storage):
+    """Several particles of several rounds in one handle: bitwise each channel
+    alone (FP32, FP64), and the oracle within the FP64 bar."""
+    chans = _multi_round_channels(storage)
+    s, g = run_gpu(chans, 120)
+    s.close()
+    pid = 0
+    for ci, (cfg, parts) in enumerate(chans):
+        s1, g1 = run_gpu([(cfg, parts)], 120)
+        s1.close()
+        n = len(parts)
+        assert np.array_equal(g[:, pid:pid + n, :9], g1[:, :, :9]), ci
+        if storage == C.STORE_F64:
+            _, r = run_oracle(cfg, parts, 120)
+            for k in range(n):
+                e = series_errors(g[:, pid + k], r[:, k], body_size(parts[k]))
+                assert max(e.values()) < 1e-11, (ci, k, e)
+        pid += n
+
+
 def test_batched_persistent_grid_bitwise():
     chans = _small_ensemble(C.STORE_F32)
     _, a = run_gpu(chans, 120)

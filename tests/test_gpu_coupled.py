@@ -172,6 +172,23 @@ def test_combined_launch_fp64_parity_with_overlapping_patches():
     assert np.array_equal(g, h)
 
 
+def test_wide_rounds_spread_in_groups_fp64():
+    """A 120-unit square rotated by 45 degrees with markers 3 apart (160
+    markers, 3 rounds): the stencil anchors of each round of 64 markers span
+    more than the 4096-cell mask box, so every round spreads in several
+    marker groups.  FP64 against the oracle, and FP32 bitwise equal whether
+    the channel runs alone or beside another."""
+    cfg = C.couette_config(400, 240, storage=C.STORE_F64)
+    p = C.particle(shapes.square(120.0, spacing=3.0), 200.3, 120.6, 0.785)
+    errs = _compare([(cfg, [p])], 20)[0]
+    assert max(errs.values()) < 1e-11, errs
+    cfg32 = dict(cfg, storage=C.STORE_F32)
+    other = (C.couette_config(96, 48, storage=C.STORE_F32), [C.particle(shapes.circle(10.0), 40.0, 23.4, 0.0)])
+    _, g = run_gpu([other, (cfg32, [p])], 20)
+    _, h = run_gpu([(cfg32, [p])], 20)
+    assert np.array_equal(g[:, 1, :9], h[:, 0, :9])
+
+
 def test_combined_launch_rejects_other_shapes():
     from paper_1606_01805_amd import Solver
 
