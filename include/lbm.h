@@ -127,7 +127,8 @@ typedef struct lbm_tuning {
                                 rigid-body stage as one launch (both read only
                                 the step's input populations and force
                                 patches): the first workgroups take the
-                                particles, the rest take lattice tiles of
+                                particles' rounds of 64 markers, the rest
+                                take lattice tiles of
                                 64 x 9*rows_per_thread nodes.  Needs
                                 tile_w = 64 and persistent_wgs = 0 (else
                                 LBM_EINVAL); results are bitwise those of 0 */
@@ -199,7 +200,9 @@ int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t);
 int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
 
 /* Average device time per launch, in microseconds, of the three kernels of a
- * step (out_us[0] = immersed-boundary force and spreading, [1] = lattice pass,
+ * step (out_us[0] = immersed-boundary force and spreading, with the sum of
+ * the per-round partial patches of particles of more than 64 markers,
+ * [1] = lattice pass,
  * [2] = surface stress and rigid-body update), measured with HIP events on the
  * handle's stream over `reps` back-to-back launches of each kernel alone.  The
  * launches run real steps, so the state advances by reps steps per kernel
