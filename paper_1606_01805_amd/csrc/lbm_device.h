@@ -479,12 +479,15 @@ struct MlsInv {
     double i00, i01, i02, i11, i12, i22;
 };
 
-__device__ __forceinline__ MlsInv mls_inverse(const ChanDev& c, const double* w, int i0, int j0,
-                                              double x, double y, bool all) {
+// w[q] must be exactly zero at stencil nodes dropped beyond a wall: their
+// terms are then signed zeros, which leave every sum (started at +0) bitwise
+// unchanged, so the loop needs no branch.
+__device__ __forceinline__ MlsInv mls_inverse(const double* w, int i0, int j0, double x, double y,
+                                              bool all) {
     double A00 = 0.0, A01 = 0.0, A02 = 0.0, A11 = 0.0, A12 = 0.0, A22 = 0.0;
+#pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-        if (!node_valid(c, ii, jj)) continue;
         const double dx = (double)ii - x, dy = (double)jj - y, wk = w[q];
         A00 += wk;
         A01 += wk * dx;

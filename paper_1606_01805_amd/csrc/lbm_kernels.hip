@@ -147,6 +147,8 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     __shared__ double s_w[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double2 s_con[kIbmThreads];            // c_l phi_k F_l of the round
     __shared__ int2 s_anc[kRound];
+    __shared__ double s_mk[kRound][3];                 // marker: x_l, y_l, c_l
+    __shared__ double s_ml[kRound][5];                 // MLS row (i00, i01, i02), F_l
     __shared__ int s_grp[5];                           // g1, gx0, gy0, gw, gh
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     const int2 wk = a.work[blockIdx.x];
     const int pid = wk.x;
     PartDev* P = a.parts + pid;
-    const ChanDev& c = a.chan[P->chan];
+    const ChanDev c = load_chan(a.chan + P->chan);
     const int nm = P->nm, mb = P->mbeg;
     const int nr = (nm + kRound - 1) / kRound, r0 = wk.y * kRound;
     const bool lead = wk.y == 0;  // the round-0 workgroup owns the particle's bookkeeping
@@ -222,41 +224,44 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         s_w[tid] = w;
         s_ux[tid] = ux;
         s_uy[tid] = uy;
-        if (k == 0) s_anc[lo] = make_int2(m.i0, m.j0);
+        if (k == 0) {
+            s_anc[lo] = make_int2(m.i0, m.j0);
+            s_mk[lo][0] = m.xl;
+            s_mk[lo][1] = m.yl;
+            s_mk[lo][2] = c.spread_unit ? 1.0 : a.ds[mb + l];
+            // the rigid-body velocity at the marker
+            s_ml[lo][3] = V0 - Om * m.ry;
+            s_ml[lo][4] = V1 + Om * m.rx;
+        }
     }
     __syncthreads();
     if (tid < kRound) {
         // (2) per marker, all in the first wave (thread lo leads marker
-        // r0 + lo): phi, U = sum phi u* (k ascending), F = U_b - U (dt = 1)
-        // and the contributions
+        // r0 + lo): the MLS row, U = sum phi u* (k ascending) and
+        // F = U_b - U (dt = 1)
         if (r0 + tid < nm) {
-            const int lo = tid, l = r0 + lo;
-            const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
-            const double cl = c.spread_unit ? 1.0 : a.ds[mb + l];
+            const int lo = tid;
+            const int2 an = s_anc[lo];
+            const double xl = s_mk[lo][0], yl = s_mk[lo][1];
             const double* w = s_w + lo * 9;
-            const MlsInv iv = mls_inverse(c, w, m.i0, m.j0, m.xl, m.yl, false);
+            // w, u* and v* are zero at dropped nodes (phase 1), so their terms
+            // are signed zeros and need no branch
+            const MlsInv iv = mls_inverse(w, an.x, an.y, xl, yl, false);
             double Ux = 0.0, Uy = 0.0;
+#pragma unroll
             for (int q = 0; q < 9; ++q) {
-                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                if (!node_valid(c, ii, jj)) continue;
-                const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
+                const int ii = an.x + q % 3 - 1, jj = an.y + q / 3 - 1;
+                const double dx = (double)ii - xl, dy = (double)jj - yl;
                 const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
                 Ux += phi * s_ux[lo * 9 + q];
                 Uy += phi * s_uy[lo * 9 + q];
             }
-            const double ubx = V0 - Om * m.ry;
-            const double uby = V1 + Om * m.rx;
-            const double Fx = ubx - Ux, Fy = uby - Uy;
-            for (int q = 0; q < 9; ++q) {
-                const int ii = m.i0 + q % 3 - 1, jj = m.j0 + q / 3 - 1;
-                double2 v = make_double2(0.0, 0.0);
-                if (node_valid(c, ii, jj)) {
-                    const double dx = (double)ii - m.xl, dy = (double)jj - m.yl;
-                    const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
-                    v = make_double2(cl * phi * Fx, cl * phi * Fy);
-                }
-                s_con[lo * 9 + q] = v;
-            }
+            const double Fx = s_ml[lo][3] - Ux, Fy = s_ml[lo][4] - Uy;
+            s_ml[lo][0] = iv.i00;
+            s_ml[lo][1] = iv.i01;
+            s_ml[lo][2] = iv.i02;
+            s_ml[lo][3] = Fx;  // the body velocity stored here has been read
+            s_ml[lo][4] = Fy;
         }
         // the anchor box of the whole round; when it fits the masks, they
         // are set here and the round spreads as one group
@@ -279,6 +284,21 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         // covers for the lattice pass
         for (int q = tid - kRound; q < ncell; q += blockDim.x - kRound) target[q] = make_double2(0.0, 0.0);
         if (lead) mark_tiles(a, c, pid, bx0u, by0u, bw, bh, tid - kRound, blockDim.x - kRound);
+    }
+    __syncthreads();
+    // (2b) the contribution c_l phi_k F_l of each (marker, node) pair, by the
+    // pair's own thread
+    if (act) {
+        const int2 an = s_anc[lo];
+        const int ii = an.x + k % 3 - 1, jj = an.y + k / 3 - 1;
+        double2 v = make_double2(0.0, 0.0);
+        if (node_valid(c, ii, jj)) {
+            const double dx = (double)ii - s_mk[lo][0], dy = (double)jj - s_mk[lo][1];
+            const double phi = s_w[tid] * (s_ml[lo][0] + s_ml[lo][1] * dx + s_ml[lo][2] * dy);
+            const double cl = s_mk[lo][2];
+            v = make_double2(cl * phi * s_ml[lo][3], cl * phi * s_ml[lo][4]);
+        }
+        s_con[tid] = v;
     }
     __syncthreads();
     // (3) spreading: the whole round as one group, or else in groups of
@@ -524,10 +544,12 @@ template <int ST>
 __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd) {
     __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double s_t[3][kRound];
+    __shared__ double s_pg[kRound][7];  // marker: r_x, r_y, n_x, n_y, probe x, probe y, S
+    __shared__ int2 s_pa[kRound];       // probe stencil anchor
     __shared__ double sums[3];
     const int tid = threadIdx.x;
     PartDev* P = a.parts + b;
-    const ChanDev& c = a.chan[P->chan];
+    const ChanDev c = load_chan(a.chan + P->chan);
     const int nm = P->nm, mb = P->mbeg;
     const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
     const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
@@ -586,7 +608,6 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
             yp = X1 + ry + dn * nyl;
             i0 = (int)floor(xp + 0.5);
             j0 = (int)floor(yp + 0.5);
-            (void)ry;
             double dx, dy;
             int ni, nj;
             double w = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
@@ -604,26 +625,33 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
             s_r[tid] = rho;
             s_ux[tid] = ux;
             s_uy[tid] = uy;
+            if (k == 0) {
+                s_pg[lo][0] = rx;
+                s_pg[lo][1] = ry;
+                s_pg[lo][2] = nxl;
+                s_pg[lo][3] = nyl;
+                s_pg[lo][4] = xp;
+                s_pg[lo][5] = yp;
+                s_pg[lo][6] = a.ds[mb + l];
+                s_pa[lo] = make_int2(i0, j0);
+            }
         }
         __syncthreads();
         if (tid < kRound && r0 + tid < nm) {
             // marker r0 + lm, led from the first wave
             const int lm = tid, l = r0 + lm, lo = lm;
-            const double2 x = a.xi[mb + l], nb = a.nrm[mb + l];
-            const double rx = cs * x.x - sn * x.y;
-            const double ry = sn * x.x + cs * x.y;
-            const double nxl = cs * nb.x - sn * nb.y;
-            const double nyl = sn * nb.x + cs * nb.y;
-            const double xp = X0 + rx + dn * nxl;
-            const double yp = X1 + ry + dn * nyl;
-            const int i0 = (int)floor(xp + 0.5);
-            const int j0 = (int)floor(yp + 0.5);
+            const double rx = s_pg[lo][0], ry = s_pg[lo][1];
+            const double nxl = s_pg[lo][2], nyl = s_pg[lo][3];
+            const double xp = s_pg[lo][4], yp = s_pg[lo][5];
+            const int i0 = s_pa[lo].x, j0 = s_pa[lo].y;
             const double* w = s_w + lo * 9;
-            const MlsInv iv = mls_inverse(c, w, i0, j0, xp, yp, true);
+            // w is zero at dropped nodes (phase 1, with rho = 1 and u = 0
+            // there), so their terms are signed zeros and need no branch
+            const MlsInv iv = mls_inverse(w, i0, j0, xp, yp, true);
             double rP = 0.0, dudx = 0.0, dudy = 0.0, dvdx = 0.0, dvdy = 0.0;
+#pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-                if (!node_valid(c, ii, jj)) continue;
                 const double dx = (double)ii - xp, dy = (double)jj - yp;
                 const double phi = w[q] * (iv.i00 + iv.i01 * dx + iv.i02 * dy);
                 const double dpx = w[q] * (iv.i01 + iv.i11 * dx + iv.i12 * dy);
@@ -644,7 +672,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
             const double pl = pP + dn * (alx * nxl + aly * nyl);
             const double tx = txx * nxl + txy * nyl - pl * nxl;
             const double ty = txy * nxl + tyy * nyl - pl * nyl;
-            const double S = a.ds[mb + l];
+            const double S = s_pg[lo][6];
             const double t0 = tx * S, t1 = ty * S, t2 = (rx * ty - ry * tx) * S;
             if (multi) {
                 double* o = a.mscr + (long long)(mb + l) * 4;
