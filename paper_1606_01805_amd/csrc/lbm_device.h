@@ -253,33 +253,50 @@ __device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float 
     }
 }
 
-// Streamed populations f^n at one node, as FP64 f_i (all forms).
+// The nine stored values that the pull of node (x, y) reads, loaded with no
+// arithmetic on them, so that their latency can overlap other work.
 template <int ST>
-__device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c, int x, int y,
-                                              double f[9]) {
-    if constexpr (ST == ST_F64) {
-        const double* p = (const double*)fin;
+__device__ __forceinline__ void pull_load(const void* fin, const ChanDev& c, int x, int y,
+                                          typename Sto<ST>::T raw[9]) {
+    using T = typename Sto<ST>::T;
+    const T* p = (const T*)fin;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            int xs, ys;
-            pull_src(c, i, x, y, xs, ys);
-            f[i] = p[pidx(c, i, ys, xs)];
-        }
+    for (int i = 0; i < 9; ++i) {
+        int xs, ys;
+        pull_src(c, i, x, y, xs, ys);
+        raw[i] = p[pidx(c, i, ys, xs)];
+    }
+}
+
+// Streamed populations f^n at node (x, y) from its loaded values, as FP64 f_i
+// (all forms): deviations restored, walls applied.
+template <int ST>
+__device__ __forceinline__ void pull_finish_f64(const ChanDev& c, int x, int y,
+                                                const typename Sto<ST>::T raw[9], double f[9]) {
+    if constexpr (ST == ST_F64) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = raw[i];
         walls_f64(c, x, y, f);
     } else {
-        using T = typename Sto<ST>::T;
-        const T* p = (const T*)fin;
         float d[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            int xs, ys;
-            pull_src(c, i, x, y, xs, ys);
-            d[i] = load_dev<ST>(p, pidx(c, i, ys, xs), i, c);
+            if constexpr (ST == ST_F32) d[i] = raw[i];
+            else d[i] = __half2float(raw[i]) * c.isc[wclass(i)];
         }
         walls_dev(c, x, y, d);
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = wd(i) + (double)d[i];
     }
+}
+
+// Streamed populations f^n at one node, as FP64 f_i (all forms).
+template <int ST>
+__device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c, int x, int y,
+                                              double f[9]) {
+    typename Sto<ST>::T raw[9];
+    pull_load<ST>(fin, c, x, y, raw);
+    pull_finish_f64<ST>(c, x, y, raw, f);
 }
 
 // Moments of Eqs. (6), (7) before the IB force is known: rho and

@@ -563,6 +563,29 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
     const bool multi = nr > 1 && !skip;
     const double cs = skip ? 1.0 : cos(th), sn = skip ? 0.0 : sin(th);
     const int lo = tid / 9, k = tid % 9;
+    const int r0 = rnd * kRound;
+    const int l = r0 + lo;
+    const bool act = !skip && l < nm;
+    // (0) the probe stencil node of the pair and its stored populations,
+    // loaded before the neighbour list is known (only the patch forces need
+    // it), so the two latencies overlap
+    double rx = 0.0, ry = 0.0, nxl = 0.0, nyl = 0.0, xp = 0.0, yp = 0.0, dx = 0.0, dy = 0.0;
+    int i0 = 0, j0 = 0, ni = 0, nj = 0;
+    bool node = false;
+    typename Sto<ST>::T raw[9];
+    if (act) {
+        const double2 x = a.xi[mb + l], nb = a.nrm[mb + l];
+        rx = cs * x.x - sn * x.y;
+        ry = sn * x.x + cs * x.y;
+        nxl = cs * nb.x - sn * nb.y;
+        nyl = sn * nb.x + cs * nb.y;
+        xp = X0 + rx + dn * nxl;
+        yp = X1 + ry + dn * nyl;
+        i0 = (int)floor(xp + 0.5);
+        j0 = (int)floor(yp + 0.5);
+        node = stencil_node(c, i0, j0, k, xp, yp, dx, dy, ni, nj);
+        if (node) pull_load<ST>(a.fin, c, ni, nj, raw);
+    }
     // Particles of the channel whose force patches can reach this particle's
     // probe stencils (its own box grown by the probe reach), ascending.
     __shared__ int s_nb[kMaxNeighbours];
@@ -593,28 +616,12 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
     const int nnb = s_nnb;
 
     if (!skip) {
-        const int r0 = rnd * kRound;
-        const int l = r0 + lo;
-        const bool act = l < nm;
         if (act) {
-            double rx, ry, nxl, nyl, xp, yp;
-            int i0, j0;
-            const double2 x = a.xi[mb + l], nb = a.nrm[mb + l];
-            rx = cs * x.x - sn * x.y;
-            ry = sn * x.x + cs * x.y;
-            nxl = cs * nb.x - sn * nb.y;
-            nyl = sn * nb.x + cs * nb.y;
-            xp = X0 + rx + dn * nxl;
-            yp = X1 + ry + dn * nyl;
-            i0 = (int)floor(xp + 0.5);
-            j0 = (int)floor(yp + 0.5);
-            double dx, dy;
-            int ni, nj;
             double w = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
-            if (stencil_node(c, i0, j0, k, xp, yp, dx, dy, ni, nj)) {
+            if (node) {
                 w = stencil_weight(c, dx, dy);
                 double f[9], jx, jy, fx, fy;
-                pull_node_f64<ST>(a.fin, c, ni, nj, f);
+                pull_finish_f64<ST>(c, ni, nj, raw, f);
                 moments_f64(f, c, rho, jx, jy);
                 if (nnb <= kMaxNeighbours) patch_force_list(a, c, s_nb, nnb, ni, nj, fx, fy);
                 else patch_force(a, c, ni, nj, fx, fy);
