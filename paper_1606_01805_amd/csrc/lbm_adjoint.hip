@@ -198,14 +198,13 @@ __device__ __forceinline__ void zouhe_adj(int side, const double fr[9], double L
 
 // Inverse of the MLS moment matrix (as mls_inverse) with one reciprocal of
 // the determinant: the adjoint linearises the step at the taped state, where
-// the last bits of B do not matter.
-__device__ __forceinline__ MlsInv mls_inverse_adj(const ChanDev& c, const double* w, int i0, int j0, double x,
-                                                  double y) {
+// the last bits of B do not matter.  As in mls_inverse, w is zero at dropped
+// nodes, whose terms are then signed zeros, so the loop has no branch.
+__device__ __forceinline__ MlsInv mls_inverse_adj(const double* w, int i0, int j0, double x, double y) {
     double A00 = 0.0, A01 = 0.0, A02 = 0.0, A11 = 0.0, A12 = 0.0, A22 = 0.0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-        if (!node_valid(c, ii, jj)) continue;
         const double dx = (double)ii - x, dy = (double)jj - y, wk = w[q];
         A00 += wk;
         A01 += wk * dx;
@@ -615,17 +614,18 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
             const double xp = s_xp[lm][0], yp = s_xp[lm][1];
             const int i0 = s_anc[lm].x, j0 = s_anc[lm].y;
             const double* w = s_w + lm * 9;
-            const MlsInv iv = mls_inverse_adj(c, w, i0, j0, xp, yp);
+            const MlsInv iv = mls_inverse_adj(w, i0, j0, xp, yp);
             s_B[lm][0] = iv.i00;
             s_B[lm][1] = iv.i01;
             s_B[lm][2] = iv.i02;
             s_B[lm][3] = iv.i11;
             s_B[lm][4] = iv.i12;
             s_B[lm][5] = iv.i22;
+            // w is zero at dropped nodes (rho = 1, u = 0 there): no branch
             double rP = 0.0, dudx = 0.0, dudy = 0.0, dvdx = 0.0, dvdy = 0.0;
+#pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int ii = i0 + q % 3 - 1, jj = j0 + q / 3 - 1;
-                if (!node_valid(c, ii, jj)) continue;
                 const double ddx = (double)ii - xp, ddy = (double)jj - yp;
                 const double phi = w[q] * (iv.i00 + iv.i01 * ddx + iv.i02 * ddy);
                 const double dpx = w[q] * (iv.i01 + iv.i11 * ddx + iv.i12 * ddy);
@@ -899,7 +899,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
         // (2) per marker: MLS inverse
         if (lead) {
             const int lm = tid;
-            const MlsInv iv = mls_inverse_adj(c, s_w + lm * 9, s_anc[lm].x, s_anc[lm].y, s_xp[lm][0], s_xp[lm][1]);
+            const MlsInv iv = mls_inverse_adj(s_w + lm * 9, s_anc[lm].x, s_anc[lm].y, s_xp[lm][0], s_xp[lm][1]);
             s_B[lm][0] = iv.i00;
             s_B[lm][1] = iv.i01;
             s_B[lm][2] = iv.i02;
