@@ -209,6 +209,7 @@ static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     a.nwork = h->nwork;
     a.psum = h->dpsum;
     a.npsum = h->npsum;
+    a.sum_partials = 1;
     a.pcount = h->dpcount;
     a.partial = h->dpartial;
     a.mscr = h->dmscr;
@@ -520,7 +521,6 @@ static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
 static int enqueue_step(lbm_handle* h, int cur) {
     StepArgs a = make_args(h, cur);
     HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-    HIPCHK(h, launch_patch_sum(a, h->stream));
     return enqueue_rest(h, a);
 }
 
@@ -752,10 +752,7 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
         HIPCHK(h, hipEventRecord(e0, h->stream));
         for (int i = 0; i < reps; ++i) {
             StepArgs a = make_args(h, h->cur, par0);
-            if (k == 0) {
-                HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-                HIPCHK(h, launch_patch_sum(a, h->stream));
-            }
+            if (k == 0) HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
             if (k == 1) {
                 if (h->tune.overlap) {
                     // the combined launch without its particle workgroups
@@ -929,6 +926,8 @@ extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
         a.fout = h->tape_f[t];
         a.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
         a.snap = h->tape_p + (size_t)t * np;  // particle snapshot after the force stage
+        // the tape keeps the summed patches, which the adjoint kernels read
+        a.sum_partials = 0;
         HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
         HIPCHK(h, launch_patch_sum(a, h->stream));
         if ((r = enqueue_rest(h, a)) != LBM_OK) return r;

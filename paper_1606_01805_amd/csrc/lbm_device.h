@@ -316,6 +316,23 @@ __device__ __forceinline__ void moments_f64(const double f[9], const ChanDev& c,
     jy += 0.5 * c.g[1];
 }
 
+// IB force of particle P's patch at patch cell `cell`.  For a particle of
+// several rounds of kRound markers, with a.sum_partials set, it is the sum of
+// the per-round partial patches in ascending round order (the first round
+// starts the sum), exactly what the partial-sum kernel writes into the patch.
+__device__ __forceinline__ double2 patch_value(const StepArgs& a, const PartDev& P, long long cell) {
+    const int nr = (P.nm + kRound - 1) / kRound;
+    if (nr == 1 || !a.sum_partials) return a.patch[P.patch_off + cell];
+    const double2* part = a.partial + P.part_off + cell;
+    double2 acc = part[0];
+    for (int r = 1; r < nr; ++r) {
+        const double2 v = part[(long long)r * P.patch_cap];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    return acc;
+}
+
 // Force patches of a channel's particles covering node (x, y), summed in
 // ascending particle order.  Boxes hold wrapped origins on periodic axes.
 __device__ __forceinline__ void patch_force(const StepArgs& a, const ChanDev& c, int x, int y,
@@ -328,7 +345,7 @@ __device__ __forceinline__ void patch_force(const StepArgs& a, const ChanDev& c,
         if (c.bcx == 0 && dx < 0) dx += c.nx;
         if (c.bcy == 0 && dy < 0) dy += c.ny;
         if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
-            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            const double2 v = patch_value(a, P, (long long)dy * P.bw + dx);
             fx += v.x;
             fy += v.y;
         }
@@ -347,7 +364,7 @@ __device__ __forceinline__ void patch_force_list(const StepArgs& a, const ChanDe
         if (c.bcx == 0 && dx < 0) dx += c.nx;
         if (c.bcy == 0 && dy < 0) dy += c.ny;
         if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
-            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            const double2 v = patch_value(a, P, (long long)dy * P.bw + dx);
             fx += v.x;
             fy += v.y;
         }
@@ -370,7 +387,7 @@ __device__ __forceinline__ void patch_force_reg(const StepArgs& a, const ChanDev
         if (c.bcx == 0 && dx < 0) dx += c.nx;
         if (c.bcy == 0 && dy < 0) dy += c.ny;
         if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
-            double2 v = a.patch[P.patch_off + (long long)dy * P.bw + dx];
+            const double2 v = patch_value(a, P, (long long)dy * P.bw + dx);
             fx += v.x;
             fy += v.y;
         }

@@ -83,6 +83,8 @@ struct StepArgs {
     int nwork;
     int* pcount;             // [nparts] finished surface-stress workgroups; 0 between launches
     double2* partial;        // per-round partial force patches of particles of several rounds
+    int sum_partials;        // 1: readers of the patch of a particle of several rounds add
+                             // its partial patches themselves (no partial-sum launch)
     const int2* psum;        // [npsum] (particle, first cell) chunks of 256 patch cells of
                              // particles of several rounds
     int npsum;
