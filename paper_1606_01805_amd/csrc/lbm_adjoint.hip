@@ -570,15 +570,19 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
             double w = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
             if (stencil_node(c, i0, j0, k, xp, yp, dx, dy, ni, nj)) {
                 w = stencil_weight(c, dx, dy);
+                // every load of the pair first (in-order completion makes
+                // them one latency), the arithmetic after
+                typename Sto<ST>::T raw[9];
+                pull_load<ST>(a.s.fin, c, ni, nj, raw);
                 double f[9], jx, jy, fx, fy;
-                pull_node_f64<ST>(a.s.fin, c, ni, nj, f);
-                moments_f64(f, c, rho, jx, jy);
                 if (nnb <= kMaxNeighbours) {
                     double t[kAdjCell];
                     patch_terms_lds<0>(a, c, s_box, nnb, ni, nj, fx, fy, t);
                 } else {
                     fwd_force(a, c, s_nb, nnb, ni, nj, fx, fy);
                 }
+                pull_finish_f64<ST>(c, ni, nj, raw, f);
+                moments_f64(f, c, rho, jx, jy);
                 ux = (jx + 0.5 * fx) / rho;
                 uy = (jy + 0.5 * fy) / rho;
             }
@@ -862,17 +866,21 @@ __global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
             double w = 0.0, usx = 0.0, usy = 0.0, lfx = 0.0, lfy = 0.0;
             if (stencil_node(c, m.i0, m.j0, k, m.xl, m.yl, dx, dy, ni, nj)) {
                 w = stencil_weight(c, dx, dy);
+                // every load of the pair first (in-order completion makes
+                // them one latency), the arithmetic after
+                typename Sto<ST>::T raw[9];
+                pull_load<ST>(a.s.fin, c, ni, nj, raw);
                 double f[9], rho, jx, jy, fx, fy, t[kAdjCell], lfc[9];
-                pull_node_f64<ST>(a.s.fin, c, ni, nj, f);
-                moments_f64(f, c, rho, jx, jy);
-                usx = jx / rho;
-                usy = jy / rho;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lfc[i] = lam_push<ST>(a.lam_in, c, i, ni, nj);
                 // probe terms only: the marker terms are being written
                 if (nnb <= kMaxNeighbours) patch_terms_lds<3>(a, c, s_box, nnb, ni, nj, fx, fy, t);
                 else patch_terms<3>(a, c, s_nb, nnb, ni, nj, fx, fy, t);
+                pull_finish_f64<ST>(c, ni, nj, raw, f);
+                moments_f64(f, c, rho, jx, jy);
+                usx = jx / rho;
+                usy = jy / rho;
                 const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) lfc[i] = lam_push<ST>(a.lam_in, c, i, ni, nj);
                 const CollAdj ca = collide_adj(lfc, rho, ux, uy, c.g[0] + fx, c.g[1] + fy, c.tau);
                 const double lux = ca.lux + t[1], luy = ca.luy + t[2];
                 lfx = lux / (2.0 * rho) + ca.lGx;
