@@ -149,7 +149,9 @@ size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n_channels);
  * populations are initialised to the equilibrium of density 1 and the initial
  * velocity (rest or Couette) and the walls are applied.
  * Errors: LBM_EINVAL (bad field, tau <= 1/2, nx or ny < 3, two wall axes,
- * mixed storage), LBM_ENOMEM (workspace_bytes too small), LBM_EDEVICE. */
+ * mixed storage, a channel whose 9 x ny x pitch populations reach 4 GiB, with
+ * pitch = nx rounded up to 64), LBM_ENOMEM (workspace_bytes too small),
+ * LBM_EDEVICE. */
 int lbm_init(const lbm_channel_config* cfg, int32_t n_channels, void* hip_stream,
              void* workspace, size_t workspace_bytes, lbm_handle** out);
 

@@ -1092,7 +1092,7 @@ __global__ __launch_bounds__(64) void adj_lattice_kernel(AdjArgs a, int tw, int 
         pull_raw_f64<ST>(a.s.fin, c, x, y, fr);
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = fr[i];
-        walls_f64(c, x, y, f);
+        walls_f64(c, c, x, y, f);
         double rho, jx, jy;
         moments_f64(f, c, rho, jx, jy);
         double fx = 0.0, fy = 0.0, tt[kAdjCell] = {0.0, 0.0, 0.0, 0.0, 0.0};

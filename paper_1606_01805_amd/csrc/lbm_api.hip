@@ -128,6 +128,8 @@ static bool finite_all(const double* v, size_t n) {
     return true;
 }
 
+static size_t elem_size(int store) { return store == LBM_STORE_F64 ? 8 : (store == LBM_STORE_F32 ? 4 : 2); }
+
 static int validate_cfg(const lbm_channel_config& c, int idx) {
     auto bad = [&](const char* what) {
         char b[256];
@@ -137,6 +139,10 @@ static int validate_cfg(const lbm_channel_config& c, int idx) {
     };
     if (c.nx < 3 || c.ny < 3) return bad("nx and ny must be >= 3");
     if ((long long)c.nx * c.ny > (1LL << 31) / 16) return bad("lattice too large");
+    // the lattice pass addresses a channel's populations with 32-bit byte
+    // offsets: 9 planes of ny x pitch elements must stay below 4 GiB
+    if (9LL * c.ny * (((long long)c.nx + 63) / 64 * 64) * elem_size(c.storage) >= (1LL << 32))
+        return bad("channel too large for 32-bit population offsets (9 * ny * pitch * element size >= 4 GiB)");
     if (!std::isfinite(c.tau) || !(c.tau > 0.5)) return bad("tau must be finite and > 1/2");
     if ((c.bc_x != LBM_BC_PERIODIC && c.bc_x != LBM_BC_ZOUHE) ||
         (c.bc_y != LBM_BC_PERIODIC && c.bc_y != LBM_BC_ZOUHE))
@@ -169,7 +175,6 @@ static size_t buffer_bytes(const lbm_channel_config* cfg, int n, size_t elem) {
     return round_up(e * elem, 4096);
 }
 
-static size_t elem_size(int store) { return store == LBM_STORE_F64 ? 8 : (store == LBM_STORE_F32 ? 4 : 2); }
 
 extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) {
     if (!cfg || n < 1) return 0;
@@ -216,7 +221,6 @@ static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     a.flags = h->dflags;
     a.dstep = h->dstep;
     a.rec = h->drec;
-    a.max_cells = h->max_cells;
     return a;
 }
 

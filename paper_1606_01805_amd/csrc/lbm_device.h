@@ -34,6 +34,24 @@ __device__ __forceinline__ long long pidx(const ChanDev& c, int i, int y, int x)
     return c.off + (long long)i * c.plane + (long long)y * c.pitch + x;
 }
 
+// Byte offset of population i at node (x, y) from the start of the channel's
+// block.  The library admits only channels whose block is below 4 GiB, so the
+// offset is exact in 32 bits; it is zero-extended at the access, which lets
+// the access use a scalar base with a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ unsigned boff(const ChanDev& c, int i, int y, int x) {
+    return ((unsigned)i * (unsigned)c.plane + (unsigned)y * (unsigned)c.pitch + (unsigned)x) *
+           (unsigned)sizeof(T);
+}
+template <typename T>
+__device__ __forceinline__ const T& at(const char* base, unsigned off) {
+    return *(const T*)(base + off);
+}
+template <typename T>
+__device__ __forceinline__ T& at(char* base, unsigned off) {
+    return *(T*)(base + off);
+}
+
 // Source node of population i for a pull at (x, y).  Periodic axes wrap.  A
 // source beyond a wall-bounded edge is replaced by the node itself (always a
 // valid address): that population enters through the wall and is
@@ -116,23 +134,25 @@ __device__ __forceinline__ ChanDev load_chan(const ChanDev* p) {
 // lane, so the arrays are only ever indexed by constants (a store behind a
 // per-lane branch can be merged by the compiler into one store at a computed
 // index, which sends the whole array to private memory).  The pass runs only
-// if a lane of the wave lies on one of its walls.
-__device__ __forceinline__ void walls_f64(const ChanDev& c, int x, int y, double f[9]) {
+// if a lane of the wave lies on one of its walls.  The wall velocities are
+// read from w: the register copy c itself, or the descriptor in memory, so a
+// kernel with tight scalar registers loads them only in the wall rows.
+__device__ __forceinline__ void walls_f64(const ChanDev& c, const ChanDev& w, int x, int y, double f[9]) {
     const double gx = c.g[0], gy = c.g[1];
     const bool s2 = c.bcy == 1 && y == 0;
     const bool s3 = c.bcy == 1 && !s2 && y == c.ny - 1;
     if (__any(s2 || s3)) {
         // y = 0 (side 2): unknowns 2, 5, 6
-        double rho = (f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]) - 0.5 * gy) / (1.0 - c.uw[2][1]);
-        double mx = rho * c.uw[2][0] - 0.5 * gx;
-        double my = rho * c.uw[2][1] - 0.5 * gy;
+        double rho = (f[0] + f[1] + f[3] + 2.0 * (f[4] + f[7] + f[8]) - 0.5 * gy) / (1.0 - w.uw[2][1]);
+        double mx = rho * w.uw[2][0] - 0.5 * gx;
+        double my = rho * w.uw[2][1] - 0.5 * gy;
         const double a2 = f[4] + 2.0 * my / 3.0;
         const double a5 = f[7] - 0.5 * (f[1] - f[3]) + 0.5 * mx + my / 6.0;
         const double a6 = f[8] + 0.5 * (f[1] - f[3]) - 0.5 * mx + my / 6.0;
         // y = ny - 1 (side 3): unknowns 4, 7, 8
-        rho = (f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]) + 0.5 * gy) / (1.0 + c.uw[3][1]);
-        mx = rho * c.uw[3][0] - 0.5 * gx;
-        my = rho * c.uw[3][1] - 0.5 * gy;
+        rho = (f[0] + f[1] + f[3] + 2.0 * (f[2] + f[5] + f[6]) + 0.5 * gy) / (1.0 + w.uw[3][1]);
+        mx = rho * w.uw[3][0] - 0.5 * gx;
+        my = rho * w.uw[3][1] - 0.5 * gy;
         const double b4 = f[2] - 2.0 * my / 3.0;
         const double b7 = f[5] + 0.5 * (f[1] - f[3]) - 0.5 * mx - my / 6.0;
         const double b8 = f[6] - 0.5 * (f[1] - f[3]) + 0.5 * mx - my / 6.0;
@@ -147,16 +167,16 @@ __device__ __forceinline__ void walls_f64(const ChanDev& c, int x, int y, double
     const bool s1 = c.bcx == 1 && !s0 && x == c.nx - 1;
     if (__any(s0 || s1)) {
         // x = 0 (side 0): unknowns 1, 5, 8
-        double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7]) - 0.5 * gx) / (1.0 - c.uw[0][0]);
-        double mx = rho * c.uw[0][0] - 0.5 * gx;
-        double my = rho * c.uw[0][1] - 0.5 * gy;
+        double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7]) - 0.5 * gx) / (1.0 - w.uw[0][0]);
+        double mx = rho * w.uw[0][0] - 0.5 * gx;
+        double my = rho * w.uw[0][1] - 0.5 * gy;
         const double a1 = f[3] + 2.0 * mx / 3.0;
         const double a5 = f[7] - 0.5 * (f[2] - f[4]) + mx / 6.0 + 0.5 * my;
         const double a8 = f[6] + 0.5 * (f[2] - f[4]) + mx / 6.0 - 0.5 * my;
         // x = nx - 1 (side 1): unknowns 3, 7, 6
-        rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8]) + 0.5 * gx) / (1.0 + c.uw[1][0]);
-        mx = rho * c.uw[1][0] - 0.5 * gx;
-        my = rho * c.uw[1][1] - 0.5 * gy;
+        rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8]) + 0.5 * gx) / (1.0 + w.uw[1][0]);
+        mx = rho * w.uw[1][0] - 0.5 * gx;
+        my = rho * w.uw[1][1] - 0.5 * gy;
         const double b3 = f[1] - 2.0 * mx / 3.0;
         const double b7 = f[5] + 0.5 * (f[2] - f[4]) - mx / 6.0 - 0.5 * my;
         const double b6 = f[8] - 0.5 * (f[2] - f[4]) - mx / 6.0 + 0.5 * my;
@@ -194,13 +214,14 @@ __device__ __forceinline__ void store_dev(typename Sto<ST>::T* p, long long k, i
 
 // The Zou-He closures of walls_f64 written for deviations: the weights of
 // the known populations entering rho sum to 1, and w_i cancels in every
-// difference.  Same pass structure.
-__device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float d[9]) {
+// difference.  Same pass structure and the same source w of the wall
+// velocities.
+__device__ __forceinline__ void walls_dev(const ChanDev& c, const ChanDev& w, int x, int y, float d[9]) {
     const float gx = c.f_g[0], gy = c.f_g[1];
     const bool s2 = c.bcy == 1 && y == 0;
     const bool s3 = c.bcy == 1 && !s2 && y == c.ny - 1;
     if (__any(s2 || s3)) {
-        float uwx = c.f_uw[2][0], uwy = c.f_uw[2][1];
+        float uwx = w.f_uw[2][0], uwy = w.f_uw[2][1];
         float sm = d[0] + d[1] + d[3] + 2.0f * (d[4] + d[7] + d[8]);
         float rho = 1.0f + (sm - 0.5f * gy + uwy) / (1.0f - uwy);
         float mx = rho * uwx - 0.5f * gx;
@@ -208,8 +229,8 @@ __device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float 
         const float a2 = d[4] + (2.0f / 3.0f) * my;
         const float a5 = d[7] - 0.5f * (d[1] - d[3]) + 0.5f * mx + my * (1.0f / 6.0f);
         const float a6 = d[8] + 0.5f * (d[1] - d[3]) - 0.5f * mx + my * (1.0f / 6.0f);
-        uwx = c.f_uw[3][0];
-        uwy = c.f_uw[3][1];
+        uwx = w.f_uw[3][0];
+        uwy = w.f_uw[3][1];
         sm = d[0] + d[1] + d[3] + 2.0f * (d[2] + d[5] + d[6]);
         rho = 1.0f + (sm + 0.5f * gy - uwy) / (1.0f + uwy);
         mx = rho * uwx - 0.5f * gx;
@@ -227,7 +248,7 @@ __device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float 
     const bool s0 = c.bcx == 1 && x == 0;
     const bool s1 = c.bcx == 1 && !s0 && x == c.nx - 1;
     if (__any(s0 || s1)) {
-        float uwx = c.f_uw[0][0], uwy = c.f_uw[0][1];
+        float uwx = w.f_uw[0][0], uwy = w.f_uw[0][1];
         float sm = d[0] + d[2] + d[4] + 2.0f * (d[3] + d[6] + d[7]);
         float rho = 1.0f + (sm - 0.5f * gx + uwx) / (1.0f - uwx);
         float mx = rho * uwx - 0.5f * gx;
@@ -235,8 +256,8 @@ __device__ __forceinline__ void walls_dev(const ChanDev& c, int x, int y, float 
         const float a1 = d[3] + (2.0f / 3.0f) * mx;
         const float a5 = d[7] - 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) + 0.5f * my;
         const float a8 = d[6] + 0.5f * (d[2] - d[4]) + mx * (1.0f / 6.0f) - 0.5f * my;
-        uwx = c.f_uw[1][0];
-        uwy = c.f_uw[1][1];
+        uwx = w.f_uw[1][0];
+        uwy = w.f_uw[1][1];
         sm = d[0] + d[2] + d[4] + 2.0f * (d[1] + d[5] + d[8]);
         rho = 1.0f + (sm + 0.5f * gx - uwx) / (1.0f + uwx);
         mx = rho * uwx - 0.5f * gx;
@@ -276,7 +297,7 @@ __device__ __forceinline__ void pull_finish_f64(const ChanDev& c, int x, int y,
     if constexpr (ST == ST_F64) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = raw[i];
-        walls_f64(c, x, y, f);
+        walls_f64(c, c, x, y, f);
     } else {
         float d[9];
 #pragma unroll
@@ -284,7 +305,7 @@ __device__ __forceinline__ void pull_finish_f64(const ChanDev& c, int x, int y,
             if constexpr (ST == ST_F32) d[i] = raw[i];
             else d[i] = __half2float(raw[i]) * c.isc[wclass(i)];
         }
-        walls_dev(c, x, y, d);
+        walls_dev(c, c, x, y, d);
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = wd(i) + (double)d[i];
     }

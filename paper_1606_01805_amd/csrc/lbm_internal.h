@@ -73,7 +73,6 @@ struct StepArgs {
     int* flags;              // [0] unstable, [1] first bad step, [2] capacity
     long long* dstep;        // steps started so far
     double* rec;             // [kRecSlots][nparts][10]
-    int max_cells;           // force-patch cells of one particle
     int* tlist;              // [2][ntiles][kTileList] particles whose patches touch a tile
     int parity;              // which half of tlist this step fills / reads
     int tile_w, tile_h;      // tile extent in nodes

@@ -1,16 +1,21 @@
 // gfx950 kernels of the coupled LBM / MLS-IBM time step.
 //
 // Per step, in stream order:
-//   ibm_force  one workgroup per particle: marker kinematics, MLS shape
-//              functions at the markers (Sec. 1.2, Eqs. (8)-(10)), velocity
-//              interpolation from the pulled populations, Lagrangian force
-//              (Eq. (11)) and an atomic-free, deterministic spreading of
-//              c_l phi F_l into a per-particle force patch (Eq. (12)).
+//   ibm_force  one workgroup per round of 64 markers of a particle: marker
+//              kinematics, MLS shape functions at the markers (Sec. 1.2,
+//              Eqs. (8)-(10)), velocity interpolation from the pulled
+//              populations, Lagrangian force (Eq. (11)) and an atomic-free,
+//              deterministic spreading of c_l phi F_l into the particle's
+//              force patch, or into the round's partial patch for particles of
+//              several rounds (Eq. (12)).
 //   lattice    one workgroup per tile (or a persistent grid striding over the
 //              tile table of all channels): pull streaming, Zou-He walls,
 //              moments, forced BGK collision (Eqs. (2)-(7)), SoA store.
-//   traction   one workgroup per particle: probe MLS, surface stress, force
-//              and moment (Eqs. (13), (14)), BDF2 (Eqs. (15), (16)), record.
+//   traction   one workgroup per round of 64 markers: probe MLS, surface
+//              stress; the particle's last workgroup sums force and moment
+//              (Eqs. (13), (14)), advances BDF2 (Eqs. (15), (16)) and records.
+// lattice_traction runs the last two as one launch (particle workgroups
+// first), and patch_sum adds partial patches for the adjoint's tape.
 //
 // Populations are SoA: [channel block][9][ny][pitch], x fastest.  The buffer
 // read by a step holds the post-collision populations of the previous step;
@@ -379,10 +384,11 @@ __global__ __launch_bounds__(256) void patch_sum_kernel(StepArgs a) {
 // Kernel 2: the lattice pass.
 // ---------------------------------------------------------------------------
 // FP64 form, reference expression order.  f holds the pulled populations.
-__device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c, int x,
+__device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c,
+                                                  const ChanDev* cm, int x,
                                                   int y, double f[9], const int (&list)[kTileList - 1], int nlist,
-                                                  double* __restrict__ fout) {
-    walls_f64(c, x, y, f);
+                                                  char* __restrict__ fout) {
+    walls_f64(c, *cm, x, y, f);
     double rho, jx, jy;
     moments_f64(f, c, rho, jx, jy);
     double flbx = 0.0, flby = 0.0;
@@ -403,7 +409,7 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
         const double feq = wd(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
         const double Fi = pref * wd(i) * ((3.0 * (exi - ux) + 9.0 * eu * exi) * Gx +
                                           (3.0 * (eyi - uy) + 9.0 * eu * eyi) * Gy);
-        fout[pidx(c, i, y, x)] = f[i] - (f[i] - feq) / tau + Fi;
+        at<double>(fout, boff<double>(c, i, y, x)) = f[i] - (f[i] - feq) / tau + Fi;
     }
     if (!(rho > 0.0) || !isfinite(rho)) {
         a.flags[0] = 1;
@@ -413,10 +419,12 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
 
 // Reduced forms: deviations in FP32.  d holds the pulled deviations.
 template <int ST>
-__device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c, int x,
+__device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c,
+                                                  const ChanDev* cm, int x,
                                                   int y, float d[9], const int (&list)[kTileList - 1], int nlist,
-                                                  typename Sto<ST>::T* __restrict__ fout) {
-    walls_dev(c, x, y, d);
+                                                  char* __restrict__ fout) {
+    using T = typename Sto<ST>::T;
+    walls_dev(c, *cm, x, y, d);
     const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const float rho = 1.0f + drho;
     float flbx = 0.0f, flby = 0.0f;
@@ -442,7 +450,7 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
         const float deq = wf(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * usq));
         const float Fi = pref * wf(i) * ((3.0f * (exi - ux) + 9.0f * eu * exi) * Gx +
                                          (3.0f * (eyi - uy) + 9.0f * eu * eyi) * Gy);
-        store_dev<ST>(fout, pidx(c, i, y, x), i, d[i] + (deq - d[i]) * om + Fi, c);
+        store_dev<ST>(&at<T>(fout, boff<T>(c, i, y, x)), 0, i, d[i] + (deq - d[i]) * om + Fi, c);
     }
     if (!(rho > 0.0f) || !isfinite(rho)) {
         a.flags[0] = 1;
@@ -455,13 +463,18 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
 template <int ST, int TW, int NPT>
 __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, int ly) {
     using T = typename Sto<ST>::T;
-    const T* __restrict__ fin = (const T*)a.fin;
-    T* __restrict__ fout = (T*)a.fout;
     const int* tl_cur = a.tlist + (long long)a.parity * a.ntiles * kTileList;
     int* tl_next = a.tlist + (long long)(1 - a.parity) * a.ntiles * kTileList;
     const TileDev* tp = a.tiles + t;
     const int tx0 = uni(tp->x0), ty0 = uni(tp->y0);
-    const ChanDev c = load_chan(a.chan + uni(tp->chan));
+    // the descriptor in scalar registers, and in memory for the wall
+    // velocities (needed only in wall rows)
+    const ChanDev* cm = a.chan + uni(tp->chan);
+    const ChanDev c = load_chan(cm);
+    // the channel's blocks in the two buffers; accesses below add 32-bit
+    // byte offsets
+    const char* __restrict__ fin = (const char*)a.fin + c.off * (long long)sizeof(T);
+    char* __restrict__ fout = (char*)a.fout + c.off * (long long)sizeof(T);
     const int x = tx0 + lx;
     const int xl = x < c.nx ? x : c.nx - 1;  // loads of lanes past the edge stay in bounds
     // Particles whose force patches overlap this tile, appended by the
@@ -489,13 +502,13 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
             for (int i = 0; i < 9; ++i) {
                 int xs, ys;
                 pull_src(c, i, xl, yl, xs, ys);
-                f[r][i] = fin[pidx(c, i, ys, xs)];
+                f[r][i] = at<double>(fin, boff<double>(c, i, ys, xs));
             }
         }
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const int y = ty0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) collide_store_f64(a, c, x, y, f[r], list, nlist, fout);
+            if (x < c.nx && y < c.ny) collide_store_f64(a, c, cm, x, y, f[r], list, nlist, fout);
         }
     } else {
         float d[NPT][9];
@@ -507,13 +520,13 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
             for (int i = 0; i < 9; ++i) {
                 int xs, ys;
                 pull_src(c, i, xl, yl, xs, ys);
-                d[r][i] = load_dev<ST>(fin, pidx(c, i, ys, xs), i, c);
+                d[r][i] = load_dev<ST>(&at<T>(fin, boff<T>(c, i, ys, xs)), 0, i, c);
             }
         }
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const int y = ty0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, x, y, d[r], list, nlist, fout);
+            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, cm, x, y, d[r], list, nlist, fout);
         }
     }
 }

@@ -67,6 +67,24 @@ def test_invalid_configs_rejected_without_device_work(bad):
     assert L.lbm_last_error(None)
 
 
+def test_channel_block_above_4gib_rejected():
+    """The lattice pass addresses a channel's populations with 32-bit byte
+    offsets, so a channel whose 9 x ny x pitch elements reach 4 GiB is refused
+    (host-side check); a narrow tall channel just below the limit is accepted."""
+    from paper_1606_01805_amd import _lib
+
+    L = _lib.lib()
+    # nx = 3 rows are padded to a pitch of 64: 9 * 8e6 * 64 * 8 B = 36.9 GB
+    arr = (_lib.ChannelConfig * 1)(_cfg(nx=3, ny=8_000_000, storage=0))
+    assert L.lbm_workspace_bytes(arr, 1) == 0
+    h = ctypes.c_void_p()
+    assert L.lbm_init(arr, 1, None, None, 0, ctypes.byref(h)) == _lib.LBM_EINVAL and not h.value
+    assert b"32-bit" in L.lbm_last_error(None)
+    # FP16: 9 * 3_800_000 * 64 * 2 B = 4.38e9 >= 2^32 is refused, 3_600_000 rows (4.15e9) fit
+    assert L.lbm_workspace_bytes((_lib.ChannelConfig * 1)(_cfg(nx=3, ny=3_800_000, storage=2)), 1) == 0
+    assert L.lbm_workspace_bytes((_lib.ChannelConfig * 1)(_cfg(nx=3, ny=3_600_000, storage=2)), 1) > 0
+
+
 def test_mixed_storage_rejected():
     from paper_1606_01805_amd import _lib
 

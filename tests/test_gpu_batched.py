@@ -80,10 +80,15 @@ def _multi_round_channels(storage):
 @pytest.mark.parametrize("storage", [C.STORE_F32, C.STORE_F64])
 def test_batched_multi_round_particles(storage):
     """Several particles of several rounds in one handle: bitwise each channel
-    alone (FP32, FP64), and the oracle within the FP64 bar."""
+    alone (FP32, FP64) and bitwise with the combined launch, and the oracle
+    within the FP64 bar."""
     chans = _multi_round_channels(storage)
     s, g = run_gpu(chans, 120)
     s.close()
+    # the surface stress beside the lattice pass in one launch: bitwise the same
+    s2, g2 = run_gpu(chans, 120, tuning=dict(overlap=1, tile_w=64, rows_per_thread=2))
+    s2.close()
+    assert np.array_equal(g, g2)
     pid = 0
     for ci, (cfg, parts) in enumerate(chans):
         s1, g1 = run_gpu([(cfg, parts)], 120)
