@@ -443,15 +443,33 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
     const float Gx = gx + flbx, Gy = gy + flby;
     const float usq = ux * ux + uy * uy;
     const float om = c.f_omega, pref = c.f_pref;
+    // Equilibrium deviation and Guo term by pairs of opposite directions
+    // (e_j = -e_i): e.u and e.G change sign, their product and squares do
+    // not, so with
+    //   C = drho + rho (4.5 (e.u)^2 - 1.5 u.u),  D = 3 rho e.u,
+    //   A = 9 (e.u)(e.G) - 3 u.G,                B = 3 e.G,
+    // deq_i = w (C + D), deq_j = w (C - D), F_i = pref w (A + B) and
+    // F_j = pref w (A - B), where deq = w (drho + rho (3 e.u + 4.5 (e.u)^2
+    // - 1.5 u.u)) and F = pref w ((3 (e - u) + 9 (e.u) e) . G) (Eqs. (4), (5)).
+    const float uG = ux * Gx + uy * Gy;
+    const float c0 = 1.5f * usq;
+    float out[9];
+    out[0] = d[0] + (wf(0) * (drho - rho * c0) - d[0]) * om + pref * wf(0) * (-3.0f * uG);
+    auto pair = [&](int i, int j, float eu, float eG) {
+        const float C = drho + rho * (4.5f * eu * eu - c0);
+        const float D = 3.0f * rho * eu;
+        const float A = 9.0f * eu * eG - 3.0f * uG;
+        const float B = 3.0f * eG;
+        const float w = wf(i), pw = pref * wf(i);
+        out[i] = d[i] + (w * (C + D) - d[i]) * om + pw * (A + B);
+        out[j] = d[j] + (w * (C - D) - d[j]) * om + pw * (A - B);
+    };
+    pair(1, 3, ux, Gx);
+    pair(2, 4, uy, Gy);
+    pair(5, 7, ux + uy, Gx + Gy);
+    pair(6, 8, uy - ux, Gy - Gx);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const float exi = (float)ex(i), eyi = (float)ey(i);
-        const float eu = exi * ux + eyi * uy;
-        const float deq = wf(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * usq));
-        const float Fi = pref * wf(i) * ((3.0f * (exi - ux) + 9.0f * eu * exi) * Gx +
-                                         (3.0f * (eyi - uy) + 9.0f * eu * eyi) * Gy);
-        store_dev<ST>(&at<T>(fout, boff<T>(c, i, y, x)), 0, i, d[i] + (deq - d[i]) * om + Fi, c);
-    }
+    for (int i = 0; i < 9; ++i) store_dev<ST>(&at<T>(fout, boff<T>(c, i, y, x)), 0, i, out[i], c);
     if (!(rho > 0.0f) || !isfinite(rho)) {
         a.flags[0] = 1;
         atomicMin(&a.flags[1], (int)(*a.dstep - 1));
