@@ -122,12 +122,22 @@ def couette_u(ny):
     return C.couette_speed(ny)
 
 
-@pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 1e-4), (C.STORE_F16S, 1e-2)])
-def test_couette_reduced_forms_trajectory_error(storage, tol):
+def _bench_tuning(name):
+    from bench import WORKLOAD_TUNING
+
+    return WORKLOAD_TUNING[name]
+
+
+@pytest.mark.parametrize("storage,tol,launch", [(C.STORE_F32, 1e-4, "default"), (C.STORE_F16S, 1e-2, "default"),
+                                                (C.STORE_F32, 1e-4, "bench")])
+def test_couette_reduced_forms_trajectory_error(storage, tol, launch):
+    """The benchmark workload (400x100 Couette, Re 20, one ellipse) over 5000
+    steps against the FP64 oracle, in the library's default launch shape and
+    in the one bench.py times (lattice pass and surface stress combined)."""
     wl = C.couette(storage=storage)
     cfg, parts = wl.channels[0]
     steps = 5000
-    s, g = run_gpu(wl.channels, steps)
+    s, g = run_gpu(wl.channels, steps, tuning=_bench_tuning("couette") if launch == "bench" else None)
     s.close()
     cfg64 = dict(cfg, storage=C.STORE_F64)
     _, r = run_oracle(cfg64, parts, steps)
