@@ -65,7 +65,7 @@ struct lbm_handle {
     double2* dnrm = nullptr;
     double* dds = nullptr;
     double2* dpatch = nullptr;
-    int2* dwork = nullptr;         // particle-kernel workgroups (particle, round)
+    int4* dwork = nullptr;         // particle-kernel workgroups (particle, round, channel, 0)
     int nwork = 0;
     int2* dpsum = nullptr;         // partial-patch sum chunks (particle, first cell)
     int npsum = 0;
@@ -475,11 +475,12 @@ static int finalize(lbm_handle* h) {
     // Particle-kernel work: one workgroup per round of kRound markers in both
     // particle kernels.  A particle of several rounds gets one partial force
     // patch per round, summed by chunks of 256 cells.
-    std::vector<int2> work, psum;
+    std::vector<int4> work;
+    std::vector<int2> psum;
     long long pcells = 0;
     for (int k = 0; k < np; ++k) {
         const int nr = (pd[k].nm + kRound - 1) / kRound;
-        for (int r = 0; r < nr; ++r) work.push_back(make_int2(k, r));
+        for (int r = 0; r < nr; ++r) work.push_back(make_int4(k, r, pd[k].chan, 0));
         pd[k].part_off = pcells;
         if (nr > 1) {
             pcells += (long long)nr * pd[k].patch_cap;
@@ -489,12 +490,12 @@ static int finalize(lbm_handle* h) {
     h->nwork = (int)work.size();
     h->npsum = (int)psum.size();
     HIPCHK(h, hipMalloc(&h->dpartial, sizeof(double2) * std::max<long long>(pcells, 1)));
-    HIPCHK(h, hipMalloc(&h->dwork, sizeof(int2) * std::max<size_t>(work.size(), 1)));
+    HIPCHK(h, hipMalloc(&h->dwork, sizeof(int4) * std::max<size_t>(work.size(), 1)));
     HIPCHK(h, hipMalloc(&h->dpsum, sizeof(int2) * std::max<size_t>(psum.size(), 1)));
     HIPCHK(h, hipMalloc(&h->dpcount, sizeof(int) * std::max(np, 1)));
     HIPCHK(h, hipMemset(h->dpcount, 0, sizeof(int) * std::max(np, 1)));
     if (!work.empty())
-        HIPCHK(h, hipMemcpy(h->dwork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->dwork, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
     if (!psum.empty())
         HIPCHK(h, hipMemcpy(h->dpsum, psum.data(), sizeof(int2) * psum.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMalloc(&h->drec, sizeof(double) * 10 * kRecSlots * std::max(np, 1)));

@@ -77,8 +77,8 @@ struct StepArgs {
     int parity;              // which half of tlist this step fills / reads
     int tile_w, tile_h;      // tile extent in nodes
     PartDev* snap;           // optional: copy of each particle after the force stage
-    const int2* work;        // [nwork] particle-kernel workgroups: (particle, round of
-                             // kRound markers), particle-major
+    const int4* work;        // [nwork] particle-kernel workgroups: (particle, round of
+                             // kRound markers, channel, 0), particle-major
     int nwork;
     int* pcount;             // [nparts] finished surface-stress workgroups; 0 between launches
     double2* partial;        // per-round partial force patches of particles of several rounds

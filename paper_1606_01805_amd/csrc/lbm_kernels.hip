@@ -158,10 +158,10 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
     if ((int)blockIdx.x >= a.nwork) return;
-    const int2 wk = a.work[blockIdx.x];
+    const int4 wk = a.work[blockIdx.x];
     const int pid = wk.x;
     PartDev* P = a.parts + pid;
-    const ChanDev c = load_chan(a.chan + P->chan);
+    const ChanDev c = load_chan(a.chan + wk.z);  // issued beside the particle's loads
     const int nm = P->nm, mb = P->mbeg;
     const int nr = (nm + kRound - 1) / kRound, r0 = wk.y * kRound;
     const bool lead = wk.y == 0;  // the round-0 workgroup owns the particle's bookkeeping
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
 // marker's traction.
 // ---------------------------------------------------------------------------
 template <int ST>
-__device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd) {
+__device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd, int ch) {
     __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double s_t[3][kRound];
     __shared__ double s_pg[kRound][7];  // marker: r_x, r_y, n_x, n_y, probe x, probe y, S
@@ -580,7 +580,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
     __shared__ double sums[3];
     const int tid = threadIdx.x;
     PartDev* P = a.parts + b;
-    const ChanDev c = load_chan(a.chan + P->chan);
+    const ChanDev c = load_chan(a.chan + ch);  // issued beside the particle's loads
     const int nm = P->nm, mb = P->mbeg;
     const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
     const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
@@ -800,8 +800,8 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd)
 template <int ST>
 __global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
     if ((int)blockIdx.x < a.nwork) {
-        const int2 wk = a.work[blockIdx.x];
-        traction_body<ST>(a, wk.x, wk.y);
+        const int4 wk = a.work[blockIdx.x];
+        traction_body<ST>(a, wk.x, wk.y, wk.z);
     }
 }
 
@@ -818,8 +818,8 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs 
     const int j = (int)blockIdx.x - tb;
     if (j < 0) {
         if ((int)blockIdx.x < a.nwork) {
-            const int2 wk = a.work[blockIdx.x];
-            traction_body<ST>(a, wk.x, wk.y);
+            const int4 wk = a.work[blockIdx.x];
+            traction_body<ST>(a, wk.x, wk.y, wk.z);
         }
         return;
     }
