@@ -457,11 +457,11 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
         pre_x = a.s.xi[mb + tid / 9];
         pre_n = a.s.nrm[mb + tid / 9];
     }
-    const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
+    const double X0 = P->X[0], X1 = P->X[1], Om = P->Om;
     const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
     if (tid < 8) s_run[tid] = 0.0;
     const double nu = c.nu, dn = c.dn;
-    const double cs = cos(th), sn = sin(th);
+    const double cs = P->cth, sn = P->sth;
 
     // adjoint patch box (covers probe and marker stencils)
     int ax0u, ay0u, aw, ah;
@@ -808,9 +808,9 @@ __global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
     const ChanDev c = load_chan(a.s.chan + P->chan);  // in registers: not re-read after each barrier
     if (A->aw <= 0) return;
     const int nm = P->nm, mb = P->mbeg;
-    const double X0 = P->X[0], X1 = P->X[1], th = P->th;
+    const double X0 = P->X[0], X1 = P->X[1];
     const double Om = P->Om, V0 = P->V[0], V1 = P->V[1];
-    const double cs = cos(th), sn = sin(th);
+    const double cs = P->cth, sn = P->sth;
     const int nnb = A->nnb;
     // marker geometry of the first round, requested early
     double2 pre_x = make_double2(0.0, 0.0);

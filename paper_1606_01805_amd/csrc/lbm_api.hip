@@ -441,6 +441,8 @@ static int finalize(lbm_handle* h) {
         q.X[0] = q.Xm[0] = P.d.x;
         q.X[1] = q.Xm[1] = P.d.y;
         q.th = q.thm = P.d.theta;
+        q.cth = std::cos(q.th);
+        q.sth = std::sin(q.th);
         q.V[0] = q.Vm[0] = P.d.u;
         q.V[1] = q.Vm[1] = P.d.v;
         q.Om = q.Omm = P.d.omega;

@@ -43,6 +43,7 @@ struct TileDev {
 // Rigid particle state (FP64) plus its force patch.
 struct PartDev {
     double X[2], Xm[2], th, thm;
+    double cth, sth;         // cos(th), sin(th), evaluated once wherever th is set
     double V[2], Vm[2], Om, Omm;
     double acc[2], alp;      // accelerations of the previous step
     double F[2], M;          // force and moment of the last step

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     const bool lead = wk.y == 0;  // the round-0 workgroup owns the particle's bookkeeping
     const double X0 = P->X[0], X1 = P->X[1], th = P->th;
     const double V0 = P->V[0], V1 = P->V[1], Om = P->Om;
+    const double cs = P->cth, sn = P->sth;  // the rotation R(theta)
     // A particle whose state is no longer finite, or far outside any
     // lattice, is flagged and skipped: its stencil anchors would be
     // meaningless and must never index memory.
@@ -206,8 +207,6 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         P->bh = bh;
         if (a.snap) a.snap[pid] = *P;
     }
-    const double cs = cos(th), sn = sin(th);
-
     const int lo = tid / 9, k = tid % 9;
     const int l = r0 + lo;
     const bool act = l < nm;
@@ -592,7 +591,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     if (skip && rnd > 0) return;
     const int nr = (nm + kRound - 1) / kRound;
     const bool multi = nr > 1 && !skip;
-    const double cs = skip ? 1.0 : cos(th), sn = skip ? 0.0 : sin(th);
+    const double cs = skip ? 1.0 : P->cth, sn = skip ? 0.0 : P->sth;
     const int lo = tid / 9, k = tid % 9;
     const int r0 = rnd * kRound;
     const int l = r0 + lo;
@@ -771,6 +770,8 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     P->X[0] = nX0;
     P->X[1] = nX1;
     P->th = nth;
+    P->cth = cos(nth);
+    P->sth = sin(nth);
     P->acc[0] = ax;
     P->acc[1] = ay;
     P->alp = al;
