@@ -280,12 +280,12 @@ template <int ST>
 __device__ __forceinline__ void pull_load(const void* fin, const ChanDev& c, int x, int y,
                                           typename Sto<ST>::T raw[9]) {
     using T = typename Sto<ST>::T;
-    const T* p = (const T*)fin;
+    const char* base = (const char*)fin + c.off * (long long)sizeof(T);  // the channel's block
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int xs, ys;
         pull_src(c, i, x, y, xs, ys);
-        raw[i] = p[pidx(c, i, ys, xs)];
+        raw[i] = at<T>(base, boff<T>(c, i, ys, xs));
     }
 }
 
@@ -325,14 +325,12 @@ __device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c,
 __device__ __forceinline__ void moments_f64(const double f[9], const ChanDev& c, double& rho,
                                             double& jx, double& jy) {
     rho = 0.0;
-    jx = 0.0;
-    jy = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) rho += f[i];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) jx += f[i] * (double)ex(i);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) jy += f[i] * (double)ey(i);
+    // the sums of f_i e_i in ascending i over the directions with e != 0
+    // (the others add signed zeros, which change no nonzero sum)
+    jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+    jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
     jx += 0.5 * c.g[0];
     jy += 0.5 * c.g[1];
 }
@@ -471,8 +469,14 @@ __device__ __forceinline__ double kernel_weight(int kind, double r, double alpha
 
 __device__ __forceinline__ int wrapc(int v, int n, int periodic) {
     if (!periodic) return v;
-    v %= n;
-    return v < 0 ? v + n : v;
+    // one period either side by a conditional add; the remainder (an
+    // integer division) only where some lane of the wave lies further out
+    if (__any(v < -n || v >= 2 * n)) {
+        v %= n;
+        return v < 0 ? v + n : v;
+    }
+    v += v < 0 ? n : 0;
+    return v >= n ? v - n : v;
 }
 
 // Box [x0, x0 + w) x [y0, y0 + h), in unwrapped lattice coordinates, that

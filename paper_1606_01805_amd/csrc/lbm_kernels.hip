@@ -770,8 +770,6 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     P->X[0] = nX0;
     P->X[1] = nX1;
     P->th = nth;
-    P->cth = cos(nth);
-    P->sth = sin(nth);
     P->acc[0] = ax;
     P->acc[1] = ay;
     P->alp = al;
@@ -790,6 +788,12 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     r[7] = Fy;
     r[8] = Mz;
     r[9] = (double)P->chan;
+    // cos and sin of the new angle for the next step's kinematics, last so
+    // that the stores above are already on their way
+    double snt, cst;
+    sincos(nth, &snt, &cst);
+    P->cth = cst;
+    P->sth = snt;
     const bool fin = isfinite(vx) && isfinite(vy) && isfinite(om) && isfinite(nX0) &&
                      isfinite(nX1) && isfinite(nth);
     if (!fin || skip) {
