@@ -155,14 +155,23 @@ size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n_channels);
 int lbm_init(const lbm_channel_config* cfg, int32_t n_channels, void* hip_stream,
              void* workspace, size_t workspace_bytes, lbm_handle** out);
 
-/* Add a particle to `channel` before the first lbm_step.  The marker arrays
- * are copied.  The history of the
+/* Add a particle to `channel` before the first lbm_step (or after lbm_reset).
+ * The marker arrays are copied.  The history of the
  * BDF2 scheme starts equal to the initial state.
  * Errors: LBM_EINVAL (n_markers < 3, non-unit normal, non-finite or
  * non-positive value, body closer than 3 nodes to a wall, body wider than
  * the channel), LBM_ESTATE (after the first step), LBM_ECAPACITY (body too
  * large for the per-particle force patch). */
 int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_particle_desc* d, int32_t* out_id);
+
+/* Return the handle to the state lbm_init left it in, so that another run
+ * (with other particles) can use the same handle: the populations are set
+ * to each channel's initial state again (rest, or the Couette start of
+ * Sec. 3.1, as its config asks), every particle is removed, the step counter is zero, and the
+ * checkpoints, captured graphs and adjoint state are released.  The channel
+ * configs, stream, workspace and tuning are kept.  Waits for the handle's
+ * stream.  Errors: LBM_EINVAL (NULL handle), LBM_EDEVICE. */
+int lbm_reset(lbm_handle* h);
 
 /* Advance every channel by n_steps (>= 0) time steps.  If traj is not NULL
  * (host pointer) it receives [n_steps][n_particles][LBM_PSTATE]: the

@@ -57,6 +57,7 @@ SIGNATURES = {
                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
     "lbm_add_particle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ParticleDesc),
                                         ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "lbm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_get_particles": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_get_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, _dp]),

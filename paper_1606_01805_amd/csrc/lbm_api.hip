@@ -375,7 +375,7 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
 
 extern "C" int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_particle_desc* d, int32_t* out_id) {
     if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
-    if (h->finalized) FAIL(h, LBM_ESTATE, "particles can only be added before the first step");
+    if (h->finalized) FAIL(h, LBM_ESTATE, "particles can only be added before the first step (or after lbm_reset)");
     if (!d || channel < 0 || channel >= (int)h->cfg.size()) FAIL(h, LBM_EINVAL, "bad channel or descriptor");
     const int n = d->n_markers;
     if (n < 3 || n > kMaxMarkers) FAIL(h, LBM_EINVAL, "n_markers must be in 3..%d", kMaxMarkers);
@@ -717,6 +717,52 @@ extern "C" int lbm_checkpoint_restore(lbm_handle* h, int32_t slot) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->cur = c.cur;
     h->steps = c.steps;
+    return LBM_OK;
+}
+
+static void free_adjoint(lbm_handle* h);
+
+// Back to the state lbm_init leaves: the initial populations, no particles,
+// step 0.  The channel configs, the stream, the workspace and the tuning are
+// kept; the particle buffers, checkpoints, graphs and adjoint state go.
+extern "C" int lbm_reset(lbm_handle* h) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // nothing of the old run in flight
+    drop_graphs(h);
+    free_adjoint(h);
+    void** bufs[] = {(void**)&h->dparts, (void**)&h->dxi, (void**)&h->dnrm, (void**)&h->dds,
+                     (void**)&h->dpatch, (void**)&h->dmscr, (void**)&h->drec, (void**)&h->dwork,
+                     (void**)&h->dpsum, (void**)&h->dpcount, (void**)&h->dpartial};
+    for (void** p : bufs) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    for (auto& c : h->ck) {
+        if (c.f) (void)hipFree(c.f);
+        if (c.p) (void)hipFree(c.p);
+        if (c.step) (void)hipFree(c.step);
+        c = Checkpoint{};
+    }
+    h->parts.clear();
+    h->dev_of_user.clear();
+    h->user_of_dev.clear();
+    h->nparts = h->nwork = h->npsum = 0;
+    h->cells = 0;
+    h->finalized = false;
+    h->pop_modified = false;
+    h->steps = 0;
+    for (auto& ch : h->hchan) ch.p_begin = ch.p_end = 0;
+    int r;
+    if ((r = build_tiles(h)) != LBM_OK) return r;  // cleared tile lists, channel table uploaded
+    int fl[4] = {0, INT_MAX, 0, 0};
+    long long z = 0;
+    HIPCHK(h, hipMemcpy(h->dflags, fl, sizeof(fl), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->dstep, &z, sizeof(z), hipMemcpyHostToDevice));
+    StepArgs a = make_args(h, 1);  // fout = buf[0]
+    for (int c = 0; c < (int)h->cfg.size(); ++c)
+        HIPCHK(h, launch_init(h->store, a, c, h->cfg[c].init, h->cfg[c].nx, h->cfg[c].ny, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->cur = 0;
     return LBM_OK;
 }
 

@@ -120,6 +120,13 @@ class Solver:
         self._nmarkers.append(int(xi.shape[0]))
         return pid.value
 
+    def reset(self):
+        """Initial populations again, no particles, step 0 (lbm_reset)."""
+        self._chk(self._L.lbm_reset(self._h))
+        self.n_particles = 0
+        self.particle_channel = []
+        self._nmarkers = []
+
     # -- stepping --
     def step(self, n: int, record: bool = True):
         """Advance n steps; returns the [n, n_particles, 10] record or None."""

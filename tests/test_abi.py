@@ -111,5 +111,6 @@ def test_null_and_bad_arguments():
     L = _lib.lib()
     assert L.lbm_init(None, 1, None, None, 0, None) == _lib.LBM_EINVAL
     assert L.lbm_step(None, 1, None) == _lib.LBM_EINVAL
+    assert L.lbm_reset(None) == _lib.LBM_EINVAL
     assert L.lbm_destroy(None) == _lib.LBM_OK
     assert L.lbm_steps_done(None) == -1
