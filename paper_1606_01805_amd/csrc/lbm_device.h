@@ -192,13 +192,21 @@ __device__ __forceinline__ void walls_f64(const ChanDev& c, const ChanDev& w, in
 // ---------------------------------------------------------------------------
 // Reduced forms: deviations d_i = f_i - w_i in FP32.
 // ---------------------------------------------------------------------------
+// A stored F16S value h times the inverse scale 2^-(K + k_i).  The product is
+// exact in FP32, so one mixed-precision FMA (which reads the half directly)
+// gives the value of convert-then-multiply; the +0 addend (a -0 one would be
+// folded back into the multiply) only turns a -0 product into +0.
+__device__ __forceinline__ float unscale_h(__half h, float isc) {
+    return __builtin_fmaf(__half2float(h), isc, 0.0f);
+}
+
 template <int ST>
 __device__ __forceinline__ float load_dev(const typename Sto<ST>::T* p, long long k, int i,
                                           const ChanDev& c) {
     if constexpr (ST == ST_F32) {
         return p[k];
     } else {
-        return __half2float(p[k]) * c.isc[wclass(i)];
+        return unscale_h(p[k], c.isc[wclass(i)]);
     }
 }
 
@@ -303,7 +311,7 @@ __device__ __forceinline__ void pull_finish_f64(const ChanDev& c, int x, int y,
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             if constexpr (ST == ST_F32) d[i] = raw[i];
-            else d[i] = __half2float(raw[i]) * c.isc[wclass(i)];
+            else d[i] = unscale_h(raw[i], c.isc[wclass(i)]);
         }
         walls_dev(c, c, x, y, d);
 #pragma unroll
