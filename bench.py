@@ -248,7 +248,7 @@ def adjoint_leg(storage=1, steps=2000, seg=100):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the benchmark runs on one GPU only: the coupled step has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
