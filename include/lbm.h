@@ -238,7 +238,9 @@ int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]);
  * [n_particles][LBM_PSTATE] (host, particles in the order they were added)
  * and allocate a tape of max_segment steps: max_segment population buffers
  * plus force patches and particle snapshots.  Errors: LBM_EINVAL (NULL or
- * non-finite seed, probe reach wider than the channel), LBM_ENOMEM. */
+ * non-finite seed, probe reach wider than the channel, a channel whose
+ * 9 x ny x pitch adjoint populations reach 4 GiB: 8 bytes each in the FP64
+ * form, 4 in the others), LBM_ENOMEM. */
 int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_segment);
 
 /* Reverse n_steps (1..max_segment) steps that end at the current adjoint

@@ -53,7 +53,9 @@ __device__ __forceinline__ double lam_push(const void* lam, const ChanDev& c, in
     const int xd = x + ex(i), yd = y + ey(i);
     const int xs = pull_coord(xd, x, c.nx, c.bcx == 0), ys = pull_coord(yd, y, c.ny, c.bcy == 0);
     const bool ok = (c.bcx == 0 || (xd >= 0 && xd < c.nx)) && (c.bcy == 0 || (yd >= 0 && yd < c.ny));
-    const double v = (double)((const typename LamT<ST>::T*)lam)[pidx(c, i, ys, xs)];
+    using LT = typename LamT<ST>::T;
+    const char* base = (const char*)lam + c.off * (long long)sizeof(LT);  // the channel's block
+    const double v = (double)at<LT>(base, boff<LT>(c, i, ys, xs));
     return ok ? v : 0.0;
 }
 

@@ -879,6 +879,12 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
     if (np > 0 && !seed) FAIL(h, LBM_EINVAL, "seed is NULL");
     if (np > 0 && !finite_all(seed, 10 * (size_t)np)) FAIL(h, LBM_EINVAL, "non-finite seed");
     const int nch = (int)h->cfg.size();
+    // the adjoint populations are addressed like f, with 32-bit byte offsets
+    // inside a channel's block, at 8 bytes (FP64 form) or 4 bytes per value
+    const size_t lam_elem = h->store == LBM_STORE_F64 ? 8 : 4;
+    for (int c = 0; c < nch; ++c)
+        if (9 * (size_t)plane_of(h->cfg[c]) * lam_elem >= ((size_t)1 << 32))
+            FAIL(h, LBM_EINVAL, "channel %d: its adjoint populations reach 4 GiB", c);
     // adjoint patches: the stencils of the markers and of their probes
     std::vector<AdjPart> ap(std::max(np, 1));
     long long acells = 0;
@@ -915,7 +921,7 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
     free_adjoint(h);
     size_t planes = 0;
     for (auto& c : h->cfg) planes += 9 * plane_of(c);
-    h->lam_bytes = round_up(planes * (h->store == LBM_STORE_F64 ? 8 : 4), 4096);
+    h->lam_bytes = round_up(planes * lam_elem, 4096);
     const size_t nmk = std::max<size_t>(1, [&] {
         size_t m = 0;
         for (auto& p : h->parts) m += p.d.n_markers;
