@@ -267,15 +267,18 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
             s_ml[lo][3] = Fx;  // the body velocity stored here has been read
             s_ml[lo][4] = Fy;
         }
-        // the anchor box of the whole round; when it fits the masks, they
-        // are set here and the round spreads as one group
-        const bool in = tid < nact;
-        const int2 an = s_anc[in ? tid : 0];
+    } else if (tid < 2 * kRound) {
+        // meanwhile the second wave forms the anchor box of the whole round
+        // (lane j: marker r0 + j); when it fits the masks, they are set here
+        // and the round spreads as one group
+        const int j = tid - kRound;
+        const bool in = j < nact;
+        const int2 an = s_anc[in ? j : 0];
         const int x0 = wave_min(in ? an.x : INT_MAX), y0 = wave_min(in ? an.y : INT_MAX);
         const int x1 = wave_max(in ? an.x : INT_MIN), y1 = wave_max(in ? an.y : INT_MIN);
         const bool fits = (long long)(x1 - x0 + 1) * (y1 - y0 + 1) <= kMaskCells;
-        if (fits && in) atomicOr(&gmask[(an.y - y0) * (x1 - x0 + 1) + (an.x - x0)], 1ull << tid);
-        if (tid == 0) {
+        if (fits && in) atomicOr(&gmask[(an.y - y0) * (x1 - x0 + 1) + (an.x - x0)], 1ull << j);
+        if (j == 0) {
             s_grp[0] = fits ? nact : 0;
             s_grp[1] = x0;
             s_grp[2] = y0;
@@ -283,11 +286,12 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
             s_grp[4] = y1 - y0 + 1;
         }
     } else {
-        // meanwhile the other waves clear the round's target (the patch, or
-        // the round's partial patch) and the lead lists the tiles the patch
+        // and the other waves clear the round's target (the patch, or the
+        // round's partial patch), and the lead lists the tiles the patch
         // covers for the lattice pass
-        for (int q = tid - kRound; q < ncell; q += blockDim.x - kRound) target[q] = make_double2(0.0, 0.0);
-        if (lead) mark_tiles(a, c, pid, bx0u, by0u, bw, bh, tid - kRound, blockDim.x - kRound);
+        constexpr int kFirst = 2 * kRound;
+        for (int q = tid - kFirst; q < ncell; q += blockDim.x - kFirst) target[q] = make_double2(0.0, 0.0);
+        if (lead) mark_tiles(a, c, pid, bx0u, by0u, bw, bh, tid - kFirst, blockDim.x - kFirst);
     }
     __syncthreads();
     // (2b) the contribution c_l phi_k F_l of each (marker, node) pair, by the
