@@ -131,3 +131,60 @@ def test_fields_match_oracle_definition():
     o.step(30, record=False)
     for a, b in zip(s.fields(), o.fields()):
         assert np.array_equal(a, b)
+
+
+F16S_SHAPES = [dict(tile_w=128, rows_per_thread=2), dict(tile_w=256, rows_per_thread=4),
+               dict(tile_w=128, rows_per_thread=4, xcd_remap=1), dict(tile_w=256, rows_per_thread=2, persistent_wgs=5)]
+
+
+def _f16s_run(channels, steps, tuning, f=None):
+    from paper_1606_01805_amd import Solver
+
+    s = Solver(channels, storage=C.STORE_F16S, tuning=tuning)
+    if f is not None:
+        s.set_populations(f)
+    tr = s.step(steps)
+    pops = [s.populations(k) for k in range(len(channels))]
+    s.close()
+    return tr, pops
+
+
+@pytest.mark.parametrize("case", ["couette_ragged", "side_walls", "periodic_noisy", "tiny"])
+def test_f16s_launch_shapes_bitwise(case):
+    """F16S storage: tiles of width 128 and 256, more rows per thread, the
+    XCD tile order and a persistent grid give bitwise the populations of
+    64-wide tiles, with wrap, walls on either axis and ragged right edges."""
+    f = None
+    if case == "couette_ragged":
+        cfg = C.couette_config(131, 37)                  # odd width, ragged against 128 and 256
+    elif case == "side_walls":
+        cfg = C.base_config(67, 40, tau=0.7, bc_x=1, body_force=[0.0, 2e-6],
+                            u_wall=[[0.0, 0.01], [0.0, -0.02], [0, 0], [0, 0]])
+    elif case == "periodic_noisy":
+        cfg = C.base_config(258, 21, tau=0.9, body_force=[1e-5, -2e-6])
+        f = _noisy(21, 258)
+    else:
+        cfg = C.base_config(3, 3, tau=0.9, body_force=[1e-5, -2e-6])
+        f = _noisy(3, 3)
+    _, ref = _f16s_run([(cfg, [])], 60, dict(tile_w=64, rows_per_thread=2), f)
+    for tun in F16S_SHAPES:
+        _, got = _f16s_run([(cfg, [])], 60, tun, f)
+        assert np.array_equal(got[0], ref[0]), tun
+
+
+def test_f16s_launch_shapes_with_particles_bitwise():
+    """The same with force patches in the tiles: a particle crossing the
+    periodic seam in a Couette channel, batched with a second channel."""
+    from workloads import shapes
+
+    c1 = C.couette_config(261, 64)
+    p1 = C.particle(shapes.ellipse(20.0, 2.0, n_markers=50), 2.5, 30.0, 0.4)
+    c2 = C.couette_config(140, 48)
+    p2 = C.particle(shapes.circle(10.0, n_markers=32), 70.0, 20.0, 0.0)
+    chans = [(c1, [p1]), (c2, [p2])]
+    tr_ref, ref = _f16s_run(chans, 80, dict(tile_w=64, rows_per_thread=2))
+    for tun in F16S_SHAPES:
+        tr, got = _f16s_run(chans, 80, tun)
+        assert np.array_equal(tr, tr_ref), tun
+        for k in range(2):
+            assert np.array_equal(got[k], ref[k]), (tun, k)
