@@ -420,8 +420,21 @@ extern "C" int lbm_add_particle(lbm_handle* h, int32_t channel, const lbm_partic
     return LBM_OK;
 }
 
+// The device buffers finalize allocates for the particle set.
+static void free_particle_buffers(lbm_handle* h) {
+    void** bufs[] = {(void**)&h->dparts, (void**)&h->dxi, (void**)&h->dnrm, (void**)&h->dds,
+                     (void**)&h->dpatch, (void**)&h->dmscr, (void**)&h->drec, (void**)&h->dwork,
+                     (void**)&h->dpsum, (void**)&h->dpcount, (void**)&h->dpartial};
+    for (void** p : bufs) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+}
+
 static int finalize(lbm_handle* h) {
     if (h->finalized) return LBM_OK;
+    // a finalize that failed part-way left some buffers: start from none
+    free_particle_buffers(h);
     const int np = (int)h->parts.size();
     std::vector<int> order(np);
     for (int i = 0; i < np; ++i) order[i] = i;
@@ -730,13 +743,7 @@ extern "C" int lbm_reset(lbm_handle* h) {
     HIPCHK(h, hipStreamSynchronize(h->stream));  // nothing of the old run in flight
     drop_graphs(h);
     free_adjoint(h);
-    void** bufs[] = {(void**)&h->dparts, (void**)&h->dxi, (void**)&h->dnrm, (void**)&h->dds,
-                     (void**)&h->dpatch, (void**)&h->dmscr, (void**)&h->drec, (void**)&h->dwork,
-                     (void**)&h->dpsum, (void**)&h->dpcount, (void**)&h->dpartial};
-    for (void** p : bufs) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
+    free_particle_buffers(h);
     for (auto& c : h->ck) {
         if (c.f) (void)hipFree(c.f);
         if (c.p) (void)hipFree(c.p);
