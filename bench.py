@@ -125,7 +125,7 @@ def trajectory_errors(cfg, parts, ref):
 WORKLOAD_TUNING = {"couette": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1)}
 VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0),
                   "large": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
-                  "large16": dict(tile_w=256, rows_per_thread=4, xcd_remap=0)}
+                  "large16": dict(tile_w=64, rows_per_thread=4, xcd_remap=1)}
 
 
 def kernel_source_sha():
