@@ -162,7 +162,9 @@ def roofline(us_lattice, nodes, storage, traffic_key=None, tuning=None):
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "bytes_per_launch": b, "us_per_launch": us_lattice}
+            "bytes_per_launch": b, "us_per_launch": us_lattice,
+            "timing": "HIP events on the library stream around back-to-back launches of the "
+                      "kernel alone, right after the timed steps (lbm_time_kernels)"}
 
 
 def run_variant(name, storage, steps, warm, plain=False, tuning=None):
