@@ -216,8 +216,10 @@ int lbm_get_tuning(const lbm_handle* h, lbm_tuning* t);
  * [1] = lattice pass,
  * [2] = surface stress and rigid-body update), measured with HIP events on the
  * handle's stream over `reps` back-to-back launches of each kernel alone.  The
- * launches run real steps, so the state advances by reps steps per kernel
- * phase; use a checkpoint around the call to keep it.  With overlap = 1,
+ * first force launch runs before the lattice launches, so that the lattice
+ * pass works on the tile lists of a step and adds the IB force where a step
+ * does.  The launches run real steps, so the state advances by reps steps
+ * per kernel phase; use a checkpoint around the call to keep it.  With overlap = 1,
  * out_us[1] times the combined launch without its particle workgroups. */
 int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]);
 

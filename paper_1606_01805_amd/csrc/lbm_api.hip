@@ -806,11 +806,28 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
     const int par0 = h->cur;
-    const int order[3] = {1, 0, 2};  // lattice first: repeated force launches refill the tile lists
+    // The lattice pass adds the IB force in the tiles listed by the force
+    // stage of the same step, and each lattice pass clears the other parity's
+    // lists; the half read here was cleared by the last step.  So the first
+    // force launch runs before the lattice phase, filling the lists as in a
+    // step (it is timed with the other force launches), and the lattice
+    // launches follow on those lists.  Later force launches append copies,
+    // which the lattice pass drops (it sorts and deduplicates).
+    float ms_first = 0.0f;
+    {
+        HIPCHK(h, hipEventRecord(e0, h->stream));
+        StepArgs a = make_args(h, h->cur, par0);
+        HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
+        HIPCHK(h, hipEventRecord(e1, h->stream));
+        HIPCHK(h, hipEventSynchronize(e1));
+        HIPCHK(h, hipEventElapsedTime(&ms_first, e0, e1));
+    }
+    const int order[3] = {1, 0, 2};
     for (int kk = 0; kk < 3; ++kk) {
         const int k = order[kk];
+        const int n = k == 0 ? reps - 1 : reps;  // the first force launch ran above
         HIPCHK(h, hipEventRecord(e0, h->stream));
-        for (int i = 0; i < reps; ++i) {
+        for (int i = 0; i < n; ++i) {
             StepArgs a = make_args(h, h->cur, par0);
             if (k == 0) HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
             if (k == 1) {
@@ -829,6 +846,7 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
         HIPCHK(h, hipEventSynchronize(e1));
         float ms = 0;
         HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+        if (k == 0) ms += ms_first;
         out_us[k] = (k == 2 && h->nparts == 0) ? 0.0 : 1e3 * ms / reps;
     }
     (void)hipEventDestroy(e0);
