@@ -398,23 +398,50 @@ __device__ __forceinline__ void patch_force_list(const StepArgs& a, const ChanDe
     }
 }
 
-// The same sum over a list held in registers (N fixed, n <= N used, all
-// indices compile-time so the list never goes to private memory).
-template <int N>
-__device__ __forceinline__ void patch_force_reg(const StepArgs& a, const ChanDev& c,
-                                                const int (&list)[N], int n, int x, int y,
+// A listed particle's force patch as the lattice pass reads it: its box, the
+// first of its values (the patch, or the first round's partial patch when the
+// partials are summed by their readers), and the rounds and their stride.
+struct PatchRef {
+    const double2* base;
+    int bx0, by0, bw, bh;
+    int nr;                  // values added per cell (rounds of kRound markers)
+    int cap;                 // stride between the rounds' partial patches
+};
+
+__device__ __forceinline__ PatchRef patch_ref(const StepArgs& a, const PartDev& P) {
+    PatchRef R;
+    const int nr = (P.nm + kRound - 1) / kRound;
+    const bool parts = nr > 1 && a.sum_partials;
+    R.base = parts ? a.partial + P.part_off : a.patch + P.patch_off;
+    R.bx0 = P.bx0;
+    R.by0 = P.by0;
+    R.bw = P.bw;
+    R.bh = P.bh;
+    R.nr = parts ? nr : 1;
+    R.cap = P.patch_cap;
+    return R;
+}
+
+// The sum of patch_value over the particles of a tile, from their PatchRef
+// table (ascending particle index): the same terms in the same order as the
+// sum over the particle records.
+__device__ __forceinline__ void patch_force_tab(const ChanDev& c, const PatchRef* tab, int n, int x, int y,
                                                 double& fx, double& fy) {
     fx = 0.0;
     fy = 0.0;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        if (j >= n) break;
-        const PartDev& P = a.parts[list[j]];
-        int dx = x - P.bx0, dy = y - P.by0;
+    for (int j = 0; j < n; ++j) {
+        const PatchRef R = tab[j];
+        int dx = x - R.bx0, dy = y - R.by0;
         if (c.bcx == 0 && dx < 0) dx += c.nx;
         if (c.bcy == 0 && dy < 0) dy += c.ny;
-        if (dx >= 0 && dx < P.bw && dy >= 0 && dy < P.bh) {
-            const double2 v = patch_value(a, P, (long long)dy * P.bw + dx);
+        if (dx >= 0 && dx < R.bw && dy >= 0 && dy < R.bh) {
+            const double2* p = R.base + ((long long)dy * R.bw + dx);
+            double2 v = p[0];
+            for (int r = 1; r < R.nr; ++r) {
+                const double2 u = p[(long long)r * R.cap];
+                v.x += u.x;
+                v.y += u.y;
+            }
             fx += v.x;
             fy += v.y;
         }

@@ -389,14 +389,14 @@ __global__ __launch_bounds__(256) void patch_sum_kernel(StepArgs a) {
 // FP64 form, reference expression order.  f holds the pulled populations.
 __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c,
                                                   const ChanDev* cm, int x,
-                                                  int y, double f[9], const int (&list)[kTileList - 1], int nlist,
+                                                  int y, double f[9], const PatchRef* tab, int nlist,
                                                   char* __restrict__ fout) {
     walls_f64(c, *cm, x, y, f);
     double rho, jx, jy;
     moments_f64(f, c, rho, jx, jy);
     double flbx = 0.0, flby = 0.0;
     if (nlist >= kTileList) patch_force(a, c, x, y, flbx, flby);
-    else if (nlist > 0) patch_force_reg(a, c, list, nlist, x, y, flbx, flby);
+    else if (nlist > 0) patch_force_tab(c, tab, nlist, x, y, flbx, flby);
     const double gx = c.g[0], gy = c.g[1];
     const double ux = (jx + 0.5 * flbx) / rho;
     const double uy = (jy + 0.5 * flby) / rho;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
 template <int ST>
 __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c,
                                                   const ChanDev* cm, int x,
-                                                  int y, float d[9], const int (&list)[kTileList - 1], int nlist,
+                                                  int y, float d[9], const PatchRef* tab, int nlist,
                                                   char* __restrict__ fout) {
     using T = typename Sto<ST>::T;
     walls_dev(c, *cm, x, y, d);
@@ -434,7 +434,7 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
     if (nlist > 0) {
         double fx, fy;
         if (nlist >= kTileList) patch_force(a, c, x, y, fx, fy);
-        else patch_force_reg(a, c, list, nlist, x, y, fx, fy);
+        else patch_force_tab(c, tab, nlist, x, y, fx, fy);
         flbx = (float)fx;
         flby = (float)fy;
     }
@@ -512,6 +512,16 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
     } else {
         for (int j = 0; j < cnt; ++j) list_insert(list, nlist, uni(e[1 + j]));
     }
+    // The listed particles' patch references, formed once per tile in LDS
+    // (nlist is the same for the whole workgroup, so are the barriers).
+    __shared__ PatchRef s_tab[kTileList - 1];
+    if (nlist > 0 && nlist < kTileList) {
+        __syncthreads();  // a persistent workgroup's previous tile is done with the table
+#pragma unroll
+        for (int j = 0; j < kTileList - 1; ++j)
+            if (j < nlist && (int)threadIdx.x == j) s_tab[j] = patch_ref(a, a.parts[list[j]]);
+        __syncthreads();
+    }
     // all pulls of the thread's rows first, then collide and store
     if constexpr (ST == ST_F64) {
         double f[NPT][9];
@@ -529,7 +539,7 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const int y = ty0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) collide_store_f64(a, c, cm, x, y, f[r], list, nlist, fout);
+            if (x < c.nx && y < c.ny) collide_store_f64(a, c, cm, x, y, f[r], s_tab, nlist, fout);
         }
     } else {
         float d[NPT][9];
@@ -547,7 +557,7 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const int y = ty0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, cm, x, y, d[r], list, nlist, fout);
+            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, cm, x, y, d[r], s_tab, nlist, fout);
         }
     }
 }
