@@ -20,7 +20,7 @@ PSTATE = 10
 PERIODIC, ZOUHE = 0, 1
 INIT_REST, INIT_COUETTE = 0, 1
 SIDE_XLO, SIDE_XHI, SIDE_YLO, SIDE_YHI = 0, 1, 2, 3
-W_EXP, W_CUBIC, W_QUARTIC, W_COSINE = 0, 1, 2, 3
+W_EXP, W_CUBIC, W_QUARTIC, W_COSINE, W_POLY = 0, 1, 2, 3, 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)

@@ -11,7 +11,8 @@
  *   -> BDF2 rigid-body update (Eqs. (15), (16))
  *   -> streaming (left-hand side of Eq. (4)) and Zou-He walls (Sec. 1.1).
  * Everything is serial and in the most literal loop order.  No blocking, no
- * fusion, no reordering.  Readings of silent or garbled passages:
+ * fusion, no reordering beyond the summation order that reading R20 fixes.
+ * Readings of silent or garbled passages (numbered as in the design notes):
  *   R1 viscosity nu = c_s^2 (tau - 1/2)  (the printed relation is garbled)
  *   R2 rho u = sum f e + G/2 with G the total body-force vector (Eq. (7))
  *   R3 the force-corrected u enters f^eq and the forcing term
@@ -28,14 +29,22 @@
  *   R9 MLS derivatives are the linear coefficients of the fit at the probe
  *   R10 p_l = p_P + dn (a_l . n_l), from dp/dn = -rho0 a.n; a_l is the rigid
  *       acceleration of the marker lagged by one step
- *   R11 viscous stress tau = rho0 nu (grad u + grad u^T)
- *   R12 r_l runs from the centroid to the marker
- *   R13 positions and angles use the same BDF2 with the new velocity; the
- *       history at the first step is the initial state
- *   R14 m = ratio * area, I = ratio * polar moment; gravity acts on the
- *       particle only, as (1 - rho_f/rho_s) g
- *   R15 F^n and M^n, computed from level-n fields, advance the particle from
+ *   R11 viscous stress tau = rho0 nu (grad u + grad u^T); r_l runs from the
+ *       centroid to the marker
+ *   R12 positions and angles use the same BDF2 with the new velocity; the
+ *       history at the first step is the initial state; m = ratio * area,
+ *       I = ratio * polar moment; gravity acts on the particle only, as
+ *       (1 - rho_f/rho_s) g
+ *   R13 F^n and M^n, computed from level-n fields, advance the particle from
  *       n to n+1 (weak coupling, Sec. 1.3)
+ *   R14 the polynomial kernel of Eq. (20) is Peskin's four-point function
+ *       evaluated at 2 r_k (its printed break points 0.5 and 1 are those of
+ *       2 r_k = 1 and 2)
+ *   R18 force and moment sums run over the markers in ascending order
+ *   R20 the spread sum at a node is formed per particle in rounds of 64
+ *       consecutive markers (see one_step)
+ *   R23 closed boxes: a node on two walls takes the corner closure of
+ *       apply_corners (walls at rest, no fluid body force)
  */
 #include "lbm_oracle.h"
 
@@ -44,6 +53,8 @@
 #include <string.h>
 
 #define Q 9
+/* markers per round of the spreading order (reading R20) */
+#define ORC_ROUND 64
 
 /* ---------------------------------------------------------------------- */
 /* D2Q9 lattice, Sec. 1.1, Eq. (3) and the weights that follow it.          */
@@ -164,10 +175,17 @@ void orc_zouhe(int side, double f[9], double uwx, double uwy, double gx, double 
 }
 
 /* Interpolation kernels: exponential, Eq. (10); cubic, quartic and cosine,
- * Eqs. (17)-(19).  r is the distance normalised by r_w. */
+ * Eqs. (17)-(19); polynomial, Eq. (20) under reading R14: its two branches
+ * are evaluated at q = 2 r, the first for q <= 1, the second for 1 < q <= 2.
+ * r is the distance normalised by r_w. */
 double orc_kernel_weight(int kind, double r, double alpha) {
     if (r > 1.0) return 0.0;
     switch (kind) {
+        case ORC_W_POLY: {
+            double q = 2.0 * r;
+            if (q <= 1.0) return (3.0 - 2.0 * q + sqrt(1.0 + 4.0 * q - 4.0 * q * q)) / 8.0;
+            return (5.0 - 2.0 * q - sqrt(-7.0 + 12.0 * q - 4.0 * q * q)) / 8.0;
+        }
         case ORC_W_EXP: {
             double q = r / alpha;
             return exp(-(q * q));
@@ -179,7 +197,7 @@ double orc_kernel_weight(int kind, double r, double alpha) {
         case ORC_W_COSINE:
             return 0.25 * (1.0 + cos(3.14159265358979323846 / 2.0 * r));
         default:
-            return NAN; /* the printed polynomial kernel is not implemented */
+            return NAN;
     }
 }
 
@@ -282,6 +300,11 @@ struct orc_sim {
     int nx, ny;
     size_t n;
     double *f, *fc, *rho, *jx, *jy, *ux, *uy, *flbx, *flby;
+    /* spreading order (reading R20): one round's sums, one particle's sums,
+     * the nodes each has touched and their markers */
+    double *rfx, *rfy, *pfx, *pfy;
+    int32_t *rlist, *plist;
+    unsigned char *rmark, *pmark;
     int np, cap;
     particle* p;
     uint64_t anchor_hash;
@@ -296,14 +319,47 @@ static int wall_side_count(const orc_config* c) {
     return (c->bc_x == ORC_ZOUHE) + (c->bc_y == ORC_ZOUHE);
 }
 
+/* Closed-box corners (reading R23, walls at rest, no fluid body force).  A
+ * corner node lies on two walls, so five of its populations stream in from
+ * outside.  The three that point into the fluid along a wall normal or the
+ * corner diagonal take the bounce-back of their opposites; the two buried
+ * diagonal ones (parallel to neither wall normal) share what the density
+ * rho_c of the diagonal interior neighbour leaves after the other seven.
+ * (x, y): the corner; (x + sx, y + sy): its diagonal interior neighbour;
+ * in1..in3 / out1..out3: the unknown populations and their opposites;
+ * b1, b2: the buried pair. */
+static void corner_closure(orc_sim* s, int x, int y, int sx, int sy) {
+    double f[9], rc = 0.0;
+    for (int i = 0; i < Q; ++i) f[i] = s->f[idx(s, i, y, x)];
+    for (int i = 0; i < Q; ++i) rc += s->f[idx(s, i, y + sy, x + sx)];
+    /* unknown: the axis population pointing into the fluid along x and
+     * along y, and the diagonal pointing into the fluid */
+    int ix = sx > 0 ? 1 : 3, iy = sy > 0 ? 2 : 4;
+    int id = sx > 0 ? (sy > 0 ? 5 : 8) : (sy > 0 ? 6 : 7);
+    int b1 = sx == sy ? 6 : 5, b2 = sx == sy ? 8 : 7; /* the buried pair */
+    static const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    f[ix] = f[opp[ix]];
+    f[iy] = f[opp[iy]];
+    f[id] = f[opp[id]];
+    double rest = 0.0;
+    for (int i = 0; i < Q; ++i)
+        if (i != b1 && i != b2) rest += f[i];
+    double b = 0.5 * (rc - rest);
+    f[b1] = b;
+    f[b2] = b;
+    for (int i = 0; i < Q; ++i) s->f[idx(s, i, y, x)] = f[i];
+}
+
 static void apply_walls(orc_sim* s) {
     const orc_config* c = &s->cfg;
     double fl[9];
     double gx = c->body_force[0], gy = c->body_force[1];
+    /* with walls on both axes the four corner nodes take the corner closure */
+    const int box = c->bc_x == ORC_ZOUHE && c->bc_y == ORC_ZOUHE;
     if (c->bc_y == ORC_ZOUHE) {
         for (int side = ORC_SIDE_YLO; side <= ORC_SIDE_YHI; ++side) {
             int y = side == ORC_SIDE_YLO ? 0 : s->ny - 1;
-            for (int x = 0; x < s->nx; ++x) {
+            for (int x = box; x < s->nx - box; ++x) {
                 for (int i = 0; i < Q; ++i) fl[i] = s->f[idx(s, i, y, x)];
                 orc_zouhe(side, fl, c->u_wall[side][0], c->u_wall[side][1], gx, gy);
                 for (int i = 0; i < Q; ++i) s->f[idx(s, i, y, x)] = fl[i];
@@ -313,12 +369,18 @@ static void apply_walls(orc_sim* s) {
     if (c->bc_x == ORC_ZOUHE) {
         for (int side = ORC_SIDE_XLO; side <= ORC_SIDE_XHI; ++side) {
             int x = side == ORC_SIDE_XLO ? 0 : s->nx - 1;
-            for (int y = 0; y < s->ny; ++y) {
+            for (int y = box; y < s->ny - box; ++y) {
                 for (int i = 0; i < Q; ++i) fl[i] = s->f[idx(s, i, y, x)];
                 orc_zouhe(side, fl, c->u_wall[side][0], c->u_wall[side][1], gx, gy);
                 for (int i = 0; i < Q; ++i) s->f[idx(s, i, y, x)] = fl[i];
             }
         }
+    }
+    if (box) {
+        corner_closure(s, 0, 0, 1, 1);
+        corner_closure(s, s->nx - 1, 0, -1, 1);
+        corner_closure(s, 0, s->ny - 1, 1, -1);
+        corner_closure(s, s->nx - 1, s->ny - 1, -1, -1);
     }
 }
 
@@ -330,9 +392,13 @@ orc_sim* orc_create(const orc_config* cfg) {
     if ((cfg->bc_x != ORC_PERIODIC && cfg->bc_x != ORC_ZOUHE) ||
         (cfg->bc_y != ORC_PERIODIC && cfg->bc_y != ORC_ZOUHE))
         return NULL;
-    if (wall_side_count(cfg) > 1) return NULL; /* corners not supported */
+    if (wall_side_count(cfg) > 1) { /* closed box: walls at rest, no fluid force (R23) */
+        for (int k = 0; k < 4; ++k)
+            if (cfg->u_wall[k][0] != 0.0 || cfg->u_wall[k][1] != 0.0) return NULL;
+        if (cfg->body_force[0] != 0.0 || cfg->body_force[1] != 0.0) return NULL;
+    }
     if (cfg->init == ORC_INIT_COUETTE && cfg->bc_y != ORC_ZOUHE) return NULL;
-    if (cfg->mls_kernel < ORC_W_EXP || cfg->mls_kernel > ORC_W_COSINE) return NULL;
+    if (cfg->mls_kernel < ORC_W_EXP || cfg->mls_kernel > ORC_W_POLY) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->cfg = *cfg;
     s->nx = cfg->nx;
@@ -347,6 +413,14 @@ orc_sim* orc_create(const orc_config* cfg) {
     s->uy = (double*)calloc(s->n, sizeof(double));
     s->flbx = (double*)calloc(s->n, sizeof(double));
     s->flby = (double*)calloc(s->n, sizeof(double));
+    s->rfx = (double*)calloc(s->n, sizeof(double));
+    s->rfy = (double*)calloc(s->n, sizeof(double));
+    s->pfx = (double*)calloc(s->n, sizeof(double));
+    s->pfy = (double*)calloc(s->n, sizeof(double));
+    s->rlist = (int32_t*)calloc(s->n, sizeof(int32_t));
+    s->plist = (int32_t*)calloc(s->n, sizeof(int32_t));
+    s->rmark = (unsigned char*)calloc(s->n, 1);
+    s->pmark = (unsigned char*)calloc(s->n, 1);
     s->anchor_hash = 1469598103934665603ULL;
     /* Initial populations: f^eq(1, u0) (Sec. 3.1: planar Couette start), then
      * the wall reconstruction so f^0 satisfies the boundary conditions. */
@@ -384,6 +458,14 @@ void orc_destroy(orc_sim* s) {
     free(s->uy);
     free(s->flbx);
     free(s->flby);
+    free(s->rfx);
+    free(s->rfy);
+    free(s->pfx);
+    free(s->pfy);
+    free(s->rlist);
+    free(s->plist);
+    free(s->rmark);
+    free(s->pmark);
     free(s);
 }
 
@@ -587,12 +669,18 @@ static int one_step(orc_sim* s, double* rec_out) {
     /* Immersed boundary, Sec. 1.2: interpolate u* = j* / rho to every marker
      * (Eq. (8)), Lagrangian force F_l = U_b - U (Eq. (11), dt = 1), and the
      * spread f_lb(x_k) = sum_l c_l phi^l_k F_l (Eq. (12)).  Loop order:
-     * particles, markers, stencil nodes, all ascending. */
+     * particles, markers, stencil nodes, all ascending.  Eq. (12) fixes no
+     * order for the sum at a node; reading R20: a particle's markers are
+     * summed in rounds of ORC_ROUND consecutive markers, each round in
+     * ascending marker order starting from zero, the round sums are added in
+     * ascending round order, and the particles' sums are added to the node's
+     * force (zero before the first) in ascending particle order. */
     memset(s->flbx, 0, sizeof(double) * s->n);
     memset(s->flby, 0, sizeof(double) * s->n);
     for (int pi = 0; pi < s->np; ++pi) {
         particle* p = &s->p[pi];
         double cs = cos(p->th), sn = sin(p->th);
+        int np_touched = 0, nr_touched = 0;
         for (int l = 0; l < p->nm; ++l) {
             double rx = cs * p->xi[2 * l] - sn * p->xi[2 * l + 1];
             double ry = sn * p->xi[2 * l] + cs * p->xi[2 * l + 1];
@@ -615,8 +703,31 @@ static int one_step(orc_sim* s, double* rec_out) {
             for (int k = 0; k < 9; ++k) {
                 if (!ok[k]) continue;
                 size_t n = (size_t)nj[k] * nx + ni[k];
-                s->flbx[n] += cl * phi[k] * Fx;
-                s->flby[n] += cl * phi[k] * Fy;
+                if (!s->rmark[n]) { /* first term of this round at the node */
+                    s->rmark[n] = 1;
+                    s->rlist[nr_touched++] = (int32_t)n;
+                    s->rfx[n] = 0.0;
+                    s->rfy[n] = 0.0;
+                }
+                s->rfx[n] += cl * phi[k] * Fx;
+                s->rfy[n] += cl * phi[k] * Fy;
+            }
+            if ((l + 1) % ORC_ROUND == 0 || l + 1 == p->nm) {
+                /* end of a round: its sums join the particle's, in round order */
+                for (int q = 0; q < nr_touched; ++q) {
+                    size_t n = (size_t)s->rlist[q];
+                    if (!s->pmark[n]) {
+                        s->pmark[n] = 1;
+                        s->plist[np_touched++] = (int32_t)n;
+                        s->pfx[n] = s->rfx[n];
+                        s->pfy[n] = s->rfy[n];
+                    } else {
+                        s->pfx[n] += s->rfx[n];
+                        s->pfy[n] += s->rfy[n];
+                    }
+                    s->rmark[n] = 0;
+                }
+                nr_touched = 0;
             }
             double* rr = p->rec + 8 * l;
             rr[0] = xl;
@@ -627,6 +738,13 @@ static int one_step(orc_sim* s, double* rec_out) {
             rr[5] = Uy;
             rr[6] = Fx;
             rr[7] = Fy;
+        }
+        /* the particle's sums join the node's force, in particle order */
+        for (int q = 0; q < np_touched; ++q) {
+            size_t n = (size_t)s->plist[q];
+            s->flbx[n] += s->pfx[n];
+            s->flby[n] += s->pfy[n];
+            s->pmark[n] = 0;
         }
     }
 

@@ -168,3 +168,113 @@ def test_unit_spread_scale_reading():
     F = o.marker_record(0)[:, 6:8]
     fx, fy = o.last_force()
     assert np.allclose([fx.sum(), fy.sum()], F.sum(0), rtol=1e-13)
+
+
+def test_cosine_kernel_interior_values():
+    """Eq. (19) away from r = 0: W = (1 + cos(pi r / 2)) / 4 takes the closed
+    forms 3/8 at r = 2/3, (2 + sqrt 2)/8 at r = 1/2 and 1/4 at r = 1; a slip
+    in the argument scale (cos(pi r) for cos(pi r / 2)) fails every one."""
+    W = lambda r: oracle.kernel_weight(oracle.W_COSINE, r)  # noqa: E731
+    assert math.isclose(W(2.0 / 3.0), 0.375, rel_tol=0, abs_tol=2e-16)
+    assert math.isclose(W(0.5), (2.0 + math.sqrt(2.0)) / 8.0, rel_tol=0, abs_tol=2e-16)
+    assert math.isclose(W(1.0), 0.25, rel_tol=0, abs_tol=2e-16)
+    assert W(1.0 + 1e-12) == 0.0
+
+
+def _peskin_sums(W, q):
+    """For the polynomial kernel read as phi(q) = W(q / 2) (reading R14):
+    the four lattice-point values around a point at offset q in [0, 1] and
+    their even / odd sums."""
+    v = [W(q / 2.0), W((1.0 - q) / 2.0), W((1.0 + q) / 2.0), W((2.0 - q) / 2.0)]
+    return sum(v), v[0] + v[3], v[1] + v[2]
+
+
+def test_polynomial_kernel_reading():
+    """Eq. (20) under reading R14 (the branches evaluated at q = 2 r): W(0) =
+    1/2, both branches give 1/4 at r = 1/2, W(1) = 0.  The function is the
+    four-point delta function, so at every offset its four lattice values sum
+    to 1 and the even and odd pairs to 1/2 each; a wrong sign, coefficient or
+    branch point in either branch breaks these sums."""
+    W = lambda r: oracle.kernel_weight(oracle.W_POLY, r)  # noqa: E731
+    assert W(0.0) == 0.5
+    assert W(0.5) == 0.25
+    assert math.isclose(W(0.5 + 1e-13), 0.25, abs_tol=1e-12)
+    assert math.isclose(W(1.0), 0.0, abs_tol=1e-16)
+    assert W(1.0 + 1e-12) == 0.0
+    for q in np.linspace(0.0, 1.0, 41):
+        tot, even, odd = _peskin_sums(W, q)
+        assert math.isclose(tot, 1.0, abs_tol=2e-15), q
+        assert math.isclose(even, 0.5, abs_tol=2e-15), q
+        assert math.isclose(odd, 0.5, abs_tol=2e-15), q
+    r = np.linspace(0, 1, 60)
+    assert np.all(np.diff([W(v) for v in r]) < 0)
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
+def test_alternative_kernels_reproduce_linear_fields(kernel):
+    """Every kernel of Sec. 2.2 gives an MLS operator with partition of unity
+    and linear reproduction (Eqs. (8), (9))."""
+    cfg = C.base_config(64, 48, mls_kernel=kernel)
+    rng = np.random.default_rng(100 + kernel)
+    for _ in range(5):
+        x, y = rng.uniform(5, 59), rng.uniform(5, 43)
+        _, ok, phi, dx, dy = oracle.mls(cfg, x, y)
+        xk = _unwrapped_nodes(x, y)
+        assert ok.all() and np.all(phi[[4]] > 0)
+        assert math.isclose(phi.sum(), 1.0, abs_tol=1e-14)
+        assert np.allclose(phi @ xk, [x, y], atol=1e-13)
+        assert np.allclose(dx @ xk, [1.0, 0.0], atol=1e-12)
+        assert np.allclose(dy @ xk, [0.0, 1.0], atol=1e-12)
+
+
+def _spread_alone(cfg, state, parts):
+    nx, ny = cfg["nx"], cfg["ny"]
+    o = oracle.Oracle(cfg)
+    _uniform_state(o, nx, ny, state)
+    for p in parts:
+        o.add_particle(p)
+    o.step(1)
+    return o.last_force()
+
+
+def test_spread_order_adds_particle_sums():
+    """Reading R20 (Eq. (12) fixes no order): each particle's terms at a node
+    are summed on their own and the particle sums are added in ascending
+    particle order.  Two particles whose stencils share nodes therefore give
+    exactly (bitwise) the sum of their spreads alone; summing the second
+    particle's terms onto the first's running sum would not."""
+    nx, ny = 70, 50
+    cfg = C.base_config(nx, ny)
+    state = lambda x, y: (1.0 + 0.01 * math.sin(0.3 * x), 0.02 * math.sin(0.2 * y), 0.01 * math.cos(0.15 * x))  # noqa: E731
+    a = C.particle(shapes.circle(10.0, n_markers=32), 30.2, 25.1, 0.0, u=0.013)
+    b = C.particle(shapes.square(9.0), 39.7, 26.4, 0.3, v=-0.011, omega=0.003)
+    fa = _spread_alone(cfg, state, [a])
+    fb = _spread_alone(cfg, state, [b])
+    fab = _spread_alone(cfg, state, [a, b])
+    shared = (fa[0] != 0) & (fb[0] != 0)
+    assert shared.sum() > 5
+    for k in range(2):
+        assert np.array_equal(fab[k], fa[k] + fb[k])
+
+
+def test_spread_order_adds_round_sums():
+    """Reading R20: a particle of more than 64 markers sums each round of 64
+    consecutive markers on its own and adds the round sums in order, so its
+    spread is exactly the sum of the spreads of two particles made of its
+    first and its last 64 markers."""
+    nx, ny = 70, 60
+    cfg = C.base_config(nx, ny)
+    state = lambda x, y: (1.0, 0.02 * math.sin(0.2 * y + 0.1 * x), 0.01 * math.cos(0.15 * x))  # noqa: E731
+    p = C.particle(shapes.circle(16.0, n_markers=128), 34.6, 29.3, 0.2, u=0.01, omega=0.002)
+    halves = []
+    for lo in (0, 64):
+        q = dict(p)
+        for key in ("xi", "nrm", "ds"):
+            q[key] = np.asarray(p[key])[lo:lo + 64].copy()
+        halves.append(q)
+    f1 = _spread_alone(cfg, state, [halves[0]])
+    f2 = _spread_alone(cfg, state, [halves[1]])
+    f = _spread_alone(cfg, state, [p])
+    assert ((f1[0] != 0) & (f2[0] != 0)).sum() > 5
+    for k in range(2):
+        assert np.array_equal(f[k], f1[k] + f2[k])

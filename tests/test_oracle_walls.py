@@ -108,3 +108,77 @@ def test_couette_mass_drift_small():
     m0 = o.populations().sum()
     o.step(300, record=False)
     assert abs(o.populations().sum() / m0 - 1) < 1e-6
+
+
+def _box_with_bump(nx, ny, tau=0.8, amp=0.01):
+    """A closed box (Zou-He walls at rest on both axes, reading R23) holding
+    a density bump that is mirror symmetric in x and in y."""
+    o = oracle.Oracle(C.base_config(nx, ny, tau=tau, bc_x=oracle.ZOUHE, bc_y=oracle.ZOUHE))
+    f = np.zeros((9, ny, nx))
+    for y in range(ny):
+        for x in range(nx):
+            dx, dy = x - (nx - 1) / 2, y - (ny - 1) / 2
+            f[:, y, x] = oracle.equilibrium(1.0 + amp * math.exp(-(dx * dx + dy * dy) / 8.0), 0.0, 0.0)
+    o.set_populations(f)
+    return o
+
+
+def test_closed_box_corners_take_the_neighbour_density_at_rest():
+    """Reading R23: each corner node carries the density of its diagonal
+    interior neighbour and no momentum (walls at rest), and its three
+    populations that point into the fluid are the bounce-back of their
+    opposites."""
+    nx, ny = 14, 11
+    o = _box_with_bump(nx, ny)
+    o.step(37, record=False)
+    f = o.populations()
+    e, _ = oracle.lattice()
+    for (x, y, sx, sy) in ((0, 0, 1, 1), (nx - 1, 0, -1, 1), (0, ny - 1, 1, -1), (nx - 1, ny - 1, -1, -1)):
+        fc = f[:, y, x]
+        assert math.isclose(fc.sum(), f[:, y + sy, x + sx].sum(), rel_tol=0, abs_tol=4e-16)
+        assert np.abs(fc @ e).max() < 4e-17
+        for i in range(1, 9):
+            if e[i][0] in (0, sx) and e[i][1] in (0, sy):  # points into the fluid
+                j = [k for k in range(9) if (e[k] == -e[i]).all()][0]
+                assert fc[i] == fc[j]
+
+
+def test_closed_box_keeps_both_mirror_symmetries():
+    """A bump that is symmetric under x -> nx-1-x and y -> ny-1-y stays so: the
+    four corner closures and the four walls are each other's mirror images.
+    A wrong index in one corner's closure breaks this."""
+    nx, ny = 15, 12
+    o = _box_with_bump(nx, ny)
+    o.step(300, record=False)
+    f = o.populations()
+    mx = [0, 3, 2, 1, 4, 6, 5, 8, 7]  # mirror x: e_x -> -e_x
+    my = [0, 1, 4, 3, 2, 8, 7, 6, 5]  # mirror y: e_y -> -e_y
+    dev = f - oracle.lattice()[1][:, None, None]
+    scale = np.abs(dev).max()
+    assert np.abs(dev - dev[mx][:, :, ::-1]).max() < 1e-12 * scale
+    assert np.abs(dev - dev[my][:, ::-1, :]).max() < 1e-12 * scale
+    # the bump spreads: it is not trivially static
+    assert scale > 1e-4
+
+
+def test_closed_box_mass_settles():
+    """Zou-He walls fix velocities, not mass: while the bump's pressure waves
+    reach the walls the box's mass changes by a fraction of the bump's excess
+    mass, and once the flow is at rest it stays constant."""
+    o = _box_with_bump(20, 16)
+    m0 = o.populations().sum()
+    excess = m0 - 20 * 16
+    o.step(1500, record=False)
+    m1 = o.populations().sum()
+    o.step(1500, record=False)
+    m2 = o.populations().sum()
+    assert abs(m1 - m0) < 0.2 * excess
+    assert abs(m2 / m1 - 1) < 1e-12
+
+
+def test_closed_box_rejects_moving_walls_and_body_force():
+    base = dict(bc_x=oracle.ZOUHE, bc_y=oracle.ZOUHE)
+    with pytest.raises(ValueError):
+        oracle.Oracle(C.base_config(10, 10, u_wall=[[0, 0], [0, 0], [0.01, 0], [0, 0]], **base))
+    with pytest.raises(ValueError):
+        oracle.Oracle(C.base_config(10, 10, body_force=[1e-6, 0.0], **base))
