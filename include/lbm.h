@@ -61,20 +61,35 @@ enum { LBM_INIT_REST = 0, LBM_INIT_COUETTE = 1 };
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
 enum { LBM_SIDE_XLO = 0, LBM_SIDE_XHI = 1, LBM_SIDE_YLO = 2, LBM_SIDE_YHI = 3 };
 /* Interpolation kernels of Sec. 2.2: exponential (Eq. (10)), cubic, quartic
- * and cosine (Eqs. (17)-(19)). */
-enum { LBM_W_EXP = 0, LBM_W_CUBIC = 1, LBM_W_QUARTIC = 2, LBM_W_COSINE = 3 };
+ * and cosine (Eqs. (17)-(19)), and polynomial (Eq. (20)).  The printed
+ * polynomial kernel has break points 0.5 and 1 in r_k but takes the square
+ * root of a negative number between 0.5 and about 0.79; its two branches are
+ * read as functions of q = 2 r_k (break points q = 1 and 2), which makes it
+ * the four-point delta function: W(0) = 1/2, W(1/2) = 1/4, W(1) = 0. */
+enum { LBM_W_EXP = 0, LBM_W_CUBIC = 1, LBM_W_QUARTIC = 2, LBM_W_COSINE = 3, LBM_W_POLY = 4 };
 /* c_l of Eq. (12): segment length (force conservation) or 1. */
 enum { LBM_SPREAD_SEGMENT = 0, LBM_SPREAD_UNIT = 1 };
 
 #define LBM_PSTATE 10 /* per particle: x, y, theta, u, v, omega, Fx, Fy, M, channel */
-/* per particle, lbm_adjoint_gradients: dJ/d of the state at the adjoint
- * position, X(2), X_prev(2), theta, theta_prev, V(2), V_prev(2), omega,
- * omega_prev, acc(2), alpha (the lagged accelerations of Sec. 1.3), then
- * dJ/dm and dJ/dI accumulated over the reversed steps */
-#define LBM_AGRAD 17
+/* per particle, lbm_adjoint_gradients:
+ *   [0, 15)  dJ/d of the state at the adjoint position: X(2), X_prev(2),
+ *            theta, theta_prev, V(2), V_prev(2), omega, omega_prev, acc(2),
+ *            alpha (the lagged accelerations of Sec. 1.3);
+ *   15, 16   dJ/dm and dJ/dI accumulated over the reversed steps;
+ *   [17, 23) dJ/d of a start from the state at the adjoint position with the
+ *            BDF2 history equal to it (at position 0: the initial x, y,
+ *            theta, u, v, omega), i.e. the sums of the current and previous
+ *            slots;
+ *   23, 24   dJ/d area and dJ/d polar_moment (m = density_ratio * area,
+ *            I = density_ratio * polar_moment, Eqs. (15), (16)). */
+#define LBM_AGRAD 25
 
 /* One channel (an independent lattice).  Channels of one handle must share
- * `storage`.  At most one axis may carry Zou-He walls (no corners). */
+ * `storage`.  Zou-He walls on both axes make a closed box: its walls must be
+ * at rest and its body force zero, and each corner node takes the corner
+ * closure (the populations pointing into the fluid bounce back, the two
+ * buried diagonals share the density of the diagonal interior neighbour that
+ * the other seven leave); the adjoint does not support closed boxes. */
 typedef struct lbm_channel_config {
     int32_t nx, ny;          /* lattice nodes, >= 3 each */
     double tau;              /* BGK relaxation time, > 1/2 */
@@ -148,8 +163,8 @@ size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n_channels);
  * alive until lbm_destroy; NULL makes the library allocate it.  The
  * populations are initialised to the equilibrium of density 1 and the initial
  * velocity (rest or Couette) and the walls are applied.
- * Errors: LBM_EINVAL (bad field, tau <= 1/2, nx or ny < 3, two wall axes,
- * mixed storage, a channel whose 9 x ny x pitch populations reach 4 GiB, with
+ * Errors: LBM_EINVAL (bad field, tau <= 1/2, nx or ny < 3, a closed box with
+ * a moving wall or a body force, mixed storage, a channel whose 9 x ny x pitch populations reach 4 GiB, with
  * pitch = nx rounded up to 64), LBM_ENOMEM (workspace_bytes too small),
  * LBM_EDEVICE. */
 int lbm_init(const lbm_channel_config* cfg, int32_t n_channels, void* hip_stream,
@@ -256,10 +271,11 @@ int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_segment);
 int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n_steps);
 
 /* Gradients at the current adjoint position (host outputs, each may be NULL):
- *   part_out   [n_particles][LBM_AGRAD], particles in the order added; at
- *              position 0 the derivative with respect to an initial value
- *              is the sum of its current and previous slots (the BDF2
- *              history starts equal to the initial state);
+ *   part_out   [n_particles][LBM_AGRAD] (layout above), particles in the
+ *              order added; at position 0 entries [17, 25) are the
+ *              derivatives with respect to the initial pose and velocities,
+ *              the area and the polar moment (the BDF2 history starts equal
+ *              to the initial state);
  *   marker_out [sum of n_markers][5]: dJ/d xi (2), d nrm (2), d ds per
  *              marker, particles in the order added;
  *   wall_out   [n_channels][4][2]: dJ/d u_wall.  At position 0 this includes

@@ -16,7 +16,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ECAPACITY, LBM_EUNS
 STATUS_NAMES = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EDEVICE", 4: "LBM_ESTATE",
                 5: "LBM_ECAPACITY", 6: "LBM_EUNSTABLE"}
 PSTATE = 10
-AGRAD = 17
+AGRAD = 25
 STORE_F64, STORE_F32, STORE_F16S = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)

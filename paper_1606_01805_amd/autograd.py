@@ -103,10 +103,10 @@ class LBMIBMFunction(torch.autograd.Function):
         g_polar = np.zeros(npart)
         mks = [None] * npart
         for j, p in enumerate(order):
-            a = part[j]
-            g_pose[p] = [a[0] + a[2], a[1] + a[3], a[4] + a[5], a[6] + a[8], a[7] + a[9], a[10] + a[11]]
-            g_area[p] = a[15] * spec.density_ratio[p]
-            g_polar[p] = a[16] * spec.density_ratio[p]
+            # entries 17..24: initial pose and velocities, area, polar moment
+            g_pose[p] = part[j, 17:23]
+            g_area[p] = part[j, 23]
+            g_polar[p] = part[j, 24]
             mks[p] = mk[j]
         mk = np.concatenate(mks, 0)
         t = lambda v: torch.from_numpy(np.ascontiguousarray(v))

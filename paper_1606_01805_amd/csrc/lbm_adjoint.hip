@@ -84,10 +84,18 @@ __device__ __forceinline__ double kernel_dw(int kind, double r, double alpha) {
         return -8.0 + 12.0 * r;
     } else if (kind == 2) {
         return -12.0 + 24.0 * r - 12.0 * r * r;
+    } else if (kind == 3) {
+        const double h = 3.14159265358979323846 / 2.0;
+        if (r < 1e-8) return -h * h / 4.0;
+        return -0.25 * h * sin(h * r) / r;
     }
-    const double h = 3.14159265358979323846 / 2.0;
-    if (r < 1e-8) return -h * h / 4.0;
-    return -0.25 * h * sin(h * r) / r;
+    // polynomial kernel W(r) = phi(2 r): W'(r) / r = 2 phi'(2 r) / r, which
+    // tends to -4 as r -> 0 (phi(q) = 1/2 - q^2/2 + O(q^3))
+    if (r < 1e-8) return -4.0;
+    const double q = 2.0 * r;
+    const double dphi = q <= 1.0 ? (-2.0 + (2.0 - 4.0 * q) / sqrt(1.0 + 4.0 * q - 4.0 * q * q)) / 8.0
+                                 : (-2.0 - (6.0 - 4.0 * q) / sqrt(-7.0 + 12.0 * q - 4.0 * q * q)) / 8.0;
+    return 2.0 * dphi / r;
 }
 
 // Transpose of the forced collision of one node (Eqs. (4), (5)) at (rho, u, G)
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
                 } else {
                     fwd_force(a, c, s_nb, nnb, ni, nj, fx, fy);
                 }
-                pull_finish_f64<ST>(c, ni, nj, raw, f);
+                pull_finish_f64<ST>(a.s.fin, c, ni, nj, raw, f);
                 moments_f64(f, c, rho, jx, jy);
                 ux = (jx + 0.5 * fx) / rho;
                 uy = (jy + 0.5 * fy) / rho;
@@ -878,7 +886,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
                 // probe terms only: the marker terms are being written
                 if (nnb <= kMaxNeighbours) patch_terms_lds<3>(a, c, s_box, nnb, ni, nj, fx, fy, t);
                 else patch_terms<3>(a, c, s_nb, nnb, ni, nj, fx, fy, t);
-                pull_finish_f64<ST>(c, ni, nj, raw, f);
+                pull_finish_f64<ST>(a.s.fin, c, ni, nj, raw, f);
                 moments_f64(f, c, rho, jx, jy);
                 usx = jx / rho;
                 usy = jy / rho;

@@ -147,7 +147,15 @@ static int validate_cfg(const lbm_channel_config& c, int idx) {
     if ((c.bc_x != LBM_BC_PERIODIC && c.bc_x != LBM_BC_ZOUHE) ||
         (c.bc_y != LBM_BC_PERIODIC && c.bc_y != LBM_BC_ZOUHE))
         return bad("bad boundary kind");
-    if (c.bc_x == LBM_BC_ZOUHE && c.bc_y == LBM_BC_ZOUHE) return bad("walls on both axes (corners) are not supported");
+    if (c.bc_x == LBM_BC_ZOUHE && c.bc_y == LBM_BC_ZOUHE) {
+        // a closed box: its corner closure is defined for walls at rest and
+        // no fluid body force
+        for (int s = 0; s < 4; ++s)
+            if (c.u_wall[s][0] != 0.0 || c.u_wall[s][1] != 0.0)
+                return bad("a closed box (walls on both axes) needs every wall at rest");
+        if (c.body_force[0] != 0.0 || c.body_force[1] != 0.0)
+            return bad("a closed box (walls on both axes) takes no fluid body force");
+    }
     if (c.init != LBM_INIT_REST && c.init != LBM_INIT_COUETTE) return bad("bad init");
     if (c.init == LBM_INIT_COUETTE && c.bc_y != LBM_BC_ZOUHE) return bad("Couette start needs walls on y");
     if (c.storage < LBM_STORE_F64 || c.storage > LBM_STORE_F16S) return bad("bad storage");
@@ -160,7 +168,7 @@ static int validate_cfg(const lbm_channel_config& c, int idx) {
     if (!std::isfinite(c.mls_rw) || !(c.mls_rw > 2.13)) return bad("mls_rw must exceed the 3x3 stencil radius 1.5*sqrt(2)");
     if (!std::isfinite(c.mls_alpha) || !(c.mls_alpha > 0)) return bad("mls_alpha must be > 0");
     if (!std::isfinite(c.probe_dn) || c.probe_dn < 0) return bad("probe_dn must be >= 0");
-    if (c.mls_kernel < LBM_W_EXP || c.mls_kernel > LBM_W_COSINE) return bad("bad mls_kernel");
+    if (c.mls_kernel < LBM_W_EXP || c.mls_kernel > LBM_W_POLY) return bad("bad mls_kernel");
     if (c.spread_scale != LBM_SPREAD_SEGMENT && c.spread_scale != LBM_SPREAD_UNIT) return bad("bad spread_scale");
     return LBM_OK;
 }
@@ -549,15 +557,20 @@ static int run_steps(lbm_handle* h, long long n) {
     while (n > 0) {
         if (graph && n >= 2) {
             const int par = h->cur;
-            if (!h->gexec[par]) {
+            // both parities' two-step graphs are built together, so that a
+            // later call starting at the other parity (after an odd number of
+            // steps) replays without capturing
+            for (int q = 0; q < 2; ++q) {
+                const int p = (par + q) & 1;
+                if (h->gexec[p]) continue;
                 hipGraph_t g = nullptr;
                 HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-                int r1 = enqueue_step(h, par);
-                int r2 = r1 == LBM_OK ? enqueue_step(h, 1 - par) : r1;
+                int r1 = enqueue_step(h, p);
+                int r2 = r1 == LBM_OK ? enqueue_step(h, 1 - p) : r1;
                 hipError_t e = hipStreamEndCapture(h->stream, &g);
                 if (r2 != LBM_OK) return r2;
                 HIPCHK(h, e);
-                hipError_t ei = hipGraphInstantiate(&h->gexec[par], g, nullptr, nullptr, 0);
+                hipError_t ei = hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
                 HIPCHK(h, ei);
             }
@@ -907,9 +920,12 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
     // the adjoint populations are addressed like f, with 32-bit byte offsets
     // inside a channel's block, at 8 bytes (FP64 form) or 4 bytes per value
     const size_t lam_elem = h->store == LBM_STORE_F64 ? 8 : 4;
-    for (int c = 0; c < nch; ++c)
+    for (int c = 0; c < nch; ++c) {
         if (9 * (size_t)plane_of(h->cfg[c]) * lam_elem >= ((size_t)1 << 32))
             FAIL(h, LBM_EINVAL, "channel %d: its adjoint populations reach 4 GiB", c);
+        if (h->cfg[c].bc_x == LBM_BC_ZOUHE && h->cfg[c].bc_y == LBM_BC_ZOUHE)
+            FAIL(h, LBM_EINVAL, "channel %d: the adjoint has no transpose of the closed-box corner closure", c);
+    }
     // adjoint patches: the stencils of the markers and of their probes
     std::vector<AdjPart> ap(std::max(np, 1));
     long long acells = 0;
@@ -1067,10 +1083,22 @@ extern "C" int lbm_adjoint_gradients(lbm_handle* h, double* part_out, double* ma
     if (part_out)
         for (int u = 0; u < np; ++u) {
             const AdjPart& A = ap[h->dev_of_user[u]];
+            const double ratio = h->parts[u].d.density_ratio;
             double* o = part_out + (size_t)u * LBM_AGRAD;
             for (int j = 0; j < AL_N; ++j) o[j] = A.l[j];
             o[AL_N] = A.gm;
             o[AL_N + 1] = A.gI;
+            // a start with the history equal to the state: each initial value
+            // feeds both its current and its previous slot
+            double* g = o + AL_N + 2;
+            g[0] = A.l[AL_X] + A.l[AL_XM];
+            g[1] = A.l[AL_X + 1] + A.l[AL_XM + 1];
+            g[2] = A.l[AL_TH] + A.l[AL_THM];
+            g[3] = A.l[AL_V] + A.l[AL_VM];
+            g[4] = A.l[AL_V + 1] + A.l[AL_VM + 1];
+            g[5] = A.l[AL_OM] + A.l[AL_OMM];
+            g[6] = A.gm * ratio;  // m = ratio * area
+            g[7] = A.gI * ratio;  // I = ratio * polar moment
         }
     if (marker_out) {
         // device marker order follows the device particle order

@@ -282,6 +282,87 @@ __device__ __forceinline__ void walls_dev(const ChanDev& c, const ChanDev& w, in
     }
 }
 
+// Closed boxes (Zou-He walls on both axes, walls at rest, no fluid body
+// force): a corner node has five unknown populations.  The axis and
+// diagonal ones that point into the fluid bounce back their opposites; the
+// two buried diagonals (along neither wall normal) share what the density
+// rho_c of the diagonal interior neighbour leaves after the other seven.
+// The neighbour is interior, so its pulled populations need no closure.
+// (sx, sy): the direction of that neighbour.  The arrays are indexed only by
+// constants: the four corners are selected per lane.
+__device__ __forceinline__ bool corner_dir(const ChanDev& c, int x, int y, int& sx, int& sy) {
+    const bool x0 = x == 0, x1 = x == c.nx - 1, y0 = y == 0, y1 = y == c.ny - 1;
+    sx = x0 ? 1 : -1;
+    sy = y0 ? 1 : -1;
+    return (x0 || x1) && (y0 || y1);
+}
+
+template <typename V>
+__device__ __forceinline__ void corner_closure(V f[9], V rho_c, int sx, int sy, V half) {
+    const bool bl = sx > 0 && sy > 0, br = sx < 0 && sy > 0, tl = sx > 0 && sy < 0,
+               tr = sx < 0 && sy < 0;
+    const V f1 = sx > 0 ? f[3] : f[1], f3 = sx < 0 ? f[1] : f[3];
+    const V f2 = sy > 0 ? f[4] : f[2], f4 = sy < 0 ? f[2] : f[4];
+    const V f5 = bl ? f[7] : f[5], f6 = br ? f[8] : f[6];
+    const V f7 = tr ? f[5] : f[7], f8 = tl ? f[6] : f[8];
+    const bool pair68 = sx == sy;  // buried pair (6, 8), else (5, 7)
+    const V rest = pair68 ? f[0] + f1 + f2 + f3 + f4 + f5 + f7 : f[0] + f1 + f2 + f3 + f4 + f6 + f8;
+    const V b = half * (rho_c - rest);
+    f[1] = f1;
+    f[2] = f2;
+    f[3] = f3;
+    f[4] = f4;
+    f[5] = pair68 ? f5 : b;
+    f[7] = pair68 ? f7 : b;
+    f[6] = pair68 ? b : f6;
+    f[8] = pair68 ? b : f8;
+}
+
+// FP64 populations f at node (x, y) after the side closures: the corner
+// closure, with rho_c summed over the neighbour's pulled populations in
+// ascending order.  base: the channel's block of the input buffer.
+__device__ __forceinline__ void corners_f64(const char* base, const ChanDev& c, int x, int y, double f[9]) {
+    if (!(c.bcx == 1 && c.bcy == 1)) return;
+    int sx, sy;
+    const bool corner = corner_dir(c, x, y, sx, sy);
+    if (!__any(corner)) return;
+    if (corner) {
+        double rc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int xs, ys;
+            pull_src(c, i, x + sx, y + sy, xs, ys);
+            rc += at<double>(base, boff<double>(c, i, ys, xs));
+        }
+        corner_closure<double>(f, rc, sx, sy, 0.5);
+    }
+}
+
+// The same for FP32 deviations d_i = f_i - w_i: the weights of the seven
+// populations outside the buried pair sum to 17/18, which leaves
+// d_b = (drho_c - sum of the seven d) / 2 for the buried pair.
+template <int ST>
+__device__ __forceinline__ void corners_dev(const char* base, const ChanDev& c, int x, int y, float d[9]) {
+    using T = typename Sto<ST>::T;
+    if (!(c.bcx == 1 && c.bcy == 1)) return;
+    int sx, sy;
+    const bool corner = corner_dir(c, x, y, sx, sy);
+    if (!__any(corner)) return;
+    if (corner) {
+        float g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int xs, ys;
+            pull_src(c, i, x + sx, y + sy, xs, ys);
+            const T v = at<T>(base, boff<T>(c, i, ys, xs));
+            if constexpr (ST == ST_F32) g[i] = v;
+            else g[i] = unscale_h(v, c.isc[wclass(i)]);
+        }
+        const float drc = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+        corner_closure<float>(d, drc, sx, sy, 0.5f);
+    }
+}
+
 // The nine stored values that the pull of node (x, y) reads, loaded with no
 // arithmetic on them, so that their latency can overlap other work.
 template <int ST>
@@ -300,12 +381,15 @@ __device__ __forceinline__ void pull_load(const void* fin, const ChanDev& c, int
 // Streamed populations f^n at node (x, y) from its loaded values, as FP64 f_i
 // (all forms): deviations restored, walls applied.
 template <int ST>
-__device__ __forceinline__ void pull_finish_f64(const ChanDev& c, int x, int y,
+__device__ __forceinline__ void pull_finish_f64(const void* fin, const ChanDev& c, int x, int y,
                                                 const typename Sto<ST>::T raw[9], double f[9]) {
+    using T = typename Sto<ST>::T;
+    const char* base = (const char*)fin + c.off * (long long)sizeof(T);  // the channel's block
     if constexpr (ST == ST_F64) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = raw[i];
         walls_f64(c, c, x, y, f);
+        corners_f64(base, c, x, y, f);
     } else {
         float d[9];
 #pragma unroll
@@ -314,6 +398,7 @@ __device__ __forceinline__ void pull_finish_f64(const ChanDev& c, int x, int y,
             else d[i] = unscale_h(raw[i], c.isc[wclass(i)]);
         }
         walls_dev(c, c, x, y, d);
+        corners_dev<ST>(base, c, x, y, d);
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = wd(i) + (double)d[i];
     }
@@ -325,7 +410,7 @@ __device__ __forceinline__ void pull_node_f64(const void* fin, const ChanDev& c,
                                               double f[9]) {
     typename Sto<ST>::T raw[9];
     pull_load<ST>(fin, c, x, y, raw);
-    pull_finish_f64<ST>(c, x, y, raw, f);
+    pull_finish_f64<ST>(fin, c, x, y, raw, f);
 }
 
 // Moments of Eqs. (6), (7) before the IB force is known: rho and
@@ -489,6 +574,10 @@ __device__ __forceinline__ bool boxes_overlap(const ChanDev& c, int x0, int y0, 
 // moment matrix is inverted through its adjugate.  Outputs the anchor, the
 // validity mask and the value / x-derivative / y-derivative weights.
 // ---------------------------------------------------------------------------
+// Kernels of Sec. 2.2: exponential (Eq. (10)), cubic, quartic, cosine
+// (Eqs. (17)-(19)) and polynomial (Eq. (20)), the last with its two branches
+// evaluated at q = 2 r (break points q = 1 and 2: the four-point delta
+// function of immersed-boundary methods).
 __device__ __forceinline__ double kernel_weight(int kind, double r, double alpha) {
     if (r > 1.0) return 0.0;
     if (kind == 0) {
@@ -498,8 +587,12 @@ __device__ __forceinline__ double kernel_weight(int kind, double r, double alpha
         return 2.0 / 3.0 - 4.0 * r * r + 4.0 * r * r * r;
     } else if (kind == 2) {
         return 1.0 - 6.0 * r * r + 8.0 * r * r * r - 3.0 * r * r * r * r;
+    } else if (kind == 3) {
+        return 0.25 * (1.0 + cos(3.14159265358979323846 / 2.0 * r));
     }
-    return 0.25 * (1.0 + cos(3.14159265358979323846 / 2.0 * r));
+    const double q = 2.0 * r;
+    if (q <= 1.0) return (3.0 - 2.0 * q + sqrt(1.0 + 4.0 * q - 4.0 * q * q)) / 8.0;
+    return (5.0 - 2.0 * q - sqrt(-7.0 + 12.0 * q - 4.0 * q * q)) / 8.0;
 }
 
 __device__ __forceinline__ int wrapc(int v, int n, int periodic) {

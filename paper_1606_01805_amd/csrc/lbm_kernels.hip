@@ -390,8 +390,9 @@ __global__ __launch_bounds__(256) void patch_sum_kernel(StepArgs a) {
 __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c,
                                                   const ChanDev* cm, int x,
                                                   int y, double f[9], const PatchRef* tab, int nlist,
-                                                  char* __restrict__ fout) {
+                                                  const char* __restrict__ fin, char* __restrict__ fout) {
     walls_f64(c, *cm, x, y, f);
+    corners_f64(fin, c, x, y, f);
     double rho, jx, jy;
     moments_f64(f, c, rho, jx, jy);
     double flbx = 0.0, flby = 0.0;
@@ -425,9 +426,10 @@ template <int ST>
 __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c,
                                                   const ChanDev* cm, int x,
                                                   int y, float d[9], const PatchRef* tab, int nlist,
-                                                  char* __restrict__ fout) {
+                                                  const char* __restrict__ fin, char* __restrict__ fout) {
     using T = typename Sto<ST>::T;
     walls_dev(c, *cm, x, y, d);
+    corners_dev<ST>(fin, c, x, y, d);
     const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const float rho = 1.0f + drho;
     float flbx = 0.0f, flby = 0.0f;
@@ -539,7 +541,7 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const int y = ty0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) collide_store_f64(a, c, cm, x, y, f[r], s_tab, nlist, fout);
+            if (x < c.nx && y < c.ny) collide_store_f64(a, c, cm, x, y, f[r], s_tab, nlist, fin, fout);
         }
     } else {
         float d[NPT][9];
@@ -557,7 +559,7 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const int y = ty0 + ly * NPT + r;
-            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, cm, x, y, d[r], s_tab, nlist, fout);
+            if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, cm, x, y, d[r], s_tab, nlist, fin, fout);
         }
     }
 }
@@ -665,7 +667,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
             if (node) {
                 w = stencil_weight(c, dx, dy);
                 double f[9], jx, jy, fx, fy;
-                pull_finish_f64<ST>(c, ni, nj, raw, f);
+                pull_finish_f64<ST>(a.fin, c, ni, nj, raw, f);
                 moments_f64(f, c, rho, jx, jy);
                 if (nnb <= kMaxNeighbours) patch_force_list(a, c, s_nb, nnb, ni, nj, fx, fy);
                 else patch_force(a, c, ni, nj, fx, fy);

@@ -200,8 +200,8 @@ class Solver:
         return int(self._L.lbm_adjoint_position(self._h))
 
     def adjoint_gradients(self):
-        """(part [n_particles, 17], markers: list of [n_markers, 5] per
-        particle, wall [n_channels, 4, 2])."""
+        """(part [n_particles, 25] in the layout of LBM_AGRAD, markers: list
+        of [n_markers, 5] per particle, wall [n_channels, 4, 2])."""
         npart = self.n_particles
         part = np.zeros((max(npart, 1), AGRAD))
         nmk = sum(self._nmarkers)

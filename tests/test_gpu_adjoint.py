@@ -64,14 +64,18 @@ def gpu_adjoint(cfg, parts, T, c, seg=None, storage=None, tuning=None):
 
 def _params(cfg, parts, part, mk, wall):
     ratio = parts[0]["density_ratio"]
-    rows = [("x0", part[0] + part[2], FD.particle_field("x")),
-            ("y0", part[1] + part[3], FD.particle_field("y")),
-            ("theta0", part[4] + part[5], FD.particle_field("theta")),
-            ("u0", part[6] + part[8], FD.particle_field("u")),
-            ("v0", part[7] + part[9], FD.particle_field("v")),
-            ("omega0", part[10] + part[11], FD.particle_field("omega")),
-            ("area", part[15] * ratio, FD.particle_field("area")),
-            ("polar", part[16] * ratio, FD.particle_field("polar_moment"))]
+    # the library's derived entries are the slot sums and scaled mass terms
+    assert np.array_equal(part[17:23], [part[0] + part[2], part[1] + part[3], part[4] + part[5],
+                                        part[6] + part[8], part[7] + part[9], part[10] + part[11]])
+    assert part[23] == part[15] * ratio and part[24] == part[16] * ratio
+    rows = [("x0", part[17], FD.particle_field("x")),
+            ("y0", part[18], FD.particle_field("y")),
+            ("theta0", part[19], FD.particle_field("theta")),
+            ("u0", part[20], FD.particle_field("u")),
+            ("v0", part[21], FD.particle_field("v")),
+            ("omega0", part[22], FD.particle_field("omega")),
+            ("area", part[23], FD.particle_field("area")),
+            ("polar", part[24], FD.particle_field("polar_moment"))]
     for l in (0, 7, 13):
         rows += [(f"xi[{l}].x", mk[l, 0], FD.particle_field("xi", 2 * l)),
                  (f"xi[{l}].y", mk[l, 1], FD.particle_field("xi", 2 * l + 1)),

@@ -99,7 +99,7 @@ def test_batched_multi_round_particles(storage):
             _, r = run_oracle(cfg, parts, 120)
             for k in range(n):
                 e = series_errors(g[:, pid + k], r[:, k], body_size(parts[k]))
-                assert max(e.values()) < 1e-11, (ci, k, e)
+                assert max(e.values()) < 1e-12, (ci, k, e)
         pid += n
 
 

@@ -8,12 +8,18 @@ omega; largest force for Fx, Fy; force x size for M).  Dividing a series by
 its own maximum would make symmetric-zero series (e.g. the sideways motion of
 a sedimenting circle) pure rounding noise.
 
-FP64 bar: 1e-12 on flows whose density deviations are not tiny (the Couette
-cases).  For a fluid essentially at rest (the sedimentation case, |rho - 1|
-of order 1e-7) the marker pressure c_s^2 (rho - 1) is computed from a density
-near 1 held to ~1.1e-16 absolute, so a one-ulp difference of a single
-population (the two sides round exp/cos/sin differently) moves a force by
-~1e-10 of itself; the bar there is 1e-9 for forces and 1e-10 for kinematics.
+FP64 bar: 1e-12 (the Couette, periodic-seam, polygon, overlapping-particle,
+multi-round and alternative-kernel cases; both sides sum the spread in the
+order of reading R20, so only the device's exp/cos/sin, which may differ
+from the host's by one ulp, separate them).  The sedimentation case is
+ill-conditioned in that respect: the fluid is nearly at rest, every
+population near w_i carries absolute rounding noise of ~3e-17, so the density
+near 1 that gives the pressure (rho - 1)/3 is held to ~1e-16 absolute against
+pressure variations of ~1e-7, and a one-ulp change of a single kernel weight
+anywhere moves the surface force by ~3e-10 of itself.  Measured on the oracle
+alone (every exponential weight nudged by one ulp, 2000 steps): force 2.7e-10,
+velocity 1.5e-11, position 7.4e-12.  The sedimentation bars are 1e-9 for
+forces and 5e-11 for kinematics.
 """
 import math
 
@@ -48,16 +54,16 @@ def _compare(wl_channels, steps, storage=None, tuning=None):
 def test_couette_fp64_parity():
     wl = C.couette(storage=C.STORE_F64)
     errs = _compare(wl.channels, 2000)[0]
-    print({k: f"{v:.2e}" for k, v in errs.items()})
+    print({k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) < 1e-12, errs
 
 
 def test_sedimentation_fp64_parity():
     wl = C.sedimentation()
     errs = _compare(wl.channels, 2000)[0]
-    print({k: f"{v:.2e}" for k, v in errs.items()})
+    print({k: f"{v:.1e}" for k, v in errs.items()})
     for k in ("x", "y", "theta", "u", "v", "omega"):
-        assert errs[k] < 1e-10, (k, errs)
+        assert errs[k] < 5e-11, (k, errs)
     for k in ("Fx", "Fy", "M"):
         assert errs[k] < 1e-9, (k, errs)
 
@@ -69,6 +75,7 @@ def test_particle_across_periodic_edge_fp64():
     sh = shapes.ellipse(12.0, 2.0, n_markers=36)
     p = C.particle(sh, 1.3, 13.0, 0.7, u=-0.02)
     errs = _compare([(cfg, [p])], 600)[0]
+    print({k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) < 1e-12, errs
 
 
@@ -78,8 +85,9 @@ def test_three_particles_with_overlapping_patches_fp64():
     b = C.particle(shapes.square(9.0), 53.7, 31.4, 0.3)       # patch overlaps a's
     c = C.particle(shapes.triangle(10.0), 90.0, 22.0, 1.0)
     errs = _compare([(cfg, [a, b, c])], 400)
+    print([{k: f"{v:.1e}" for k, v in e.items()} for e in errs])
     for e in errs:
-        assert max(e.values()) < 1e-11, errs
+        assert max(e.values()) < 1e-12, errs
 
 
 @pytest.mark.parametrize("fam", ["square", "triangle", "rectangle"])
@@ -87,6 +95,7 @@ def test_polygon_shapes_fp64(fam):
     cfg = C.couette_config(100, 48, storage=C.STORE_F64)
     sh = shapes.make(fam, 14.0, aspect_ratio=3.0)
     errs = _compare([(cfg, [C.particle(sh, 50.0, 21.3, 0.4)])], 500)[0]
+    print({k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) < 1e-12, errs
 
 
@@ -96,15 +105,17 @@ def test_dense_markers_fp64():
     cfg = C.couette_config(80, 40, storage=C.STORE_F64)
     sh = shapes.circle(10.0, n_markers=105)
     errs = _compare([(cfg, [C.particle(sh, 40.0, 19.2, 0.0)])], 300)[0]
+    print({k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) < 1e-12, errs
 
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4])
 def test_alternative_kernels_fp64(kernel):
-    """Cubic, quartic and cosine weights (Sec. 2.2, Eqs. (17)-(19))."""
+    """Cubic, quartic, cosine and polynomial weights (Sec. 2.2, Eqs. (17)-(20))."""
     cfg = C.couette_config(80, 40, storage=C.STORE_F64, mls_kernel=kernel)
     sh = shapes.ellipse(14.0, 2.0, n_markers=40)
     errs = _compare([(cfg, [C.particle(sh, 40.0, 19.2, 0.5)])], 300)[0]
+    print({k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) < 1e-12, errs
 
 
@@ -175,8 +186,9 @@ def test_combined_launch_fp64_parity_with_overlapping_patches():
     chans = [(cfg, [a, b, c])]
     tun = dict(overlap=1, tile_w=64, rows_per_thread=2)
     errs = _compare(chans, 400, tuning=tun)
+    print([{k: f"{v:.1e}" for k, v in e.items()} for e in errs])
     for e in errs:
-        assert max(e.values()) < 1e-11, errs
+        assert max(e.values()) < 1e-12, errs
     _, g = run_gpu(chans, 200, tuning=tun)
     _, h = run_gpu(chans, 200)
     assert np.array_equal(g, h)
@@ -191,7 +203,8 @@ def test_wide_rounds_spread_in_groups_fp64():
     cfg = C.couette_config(400, 240, storage=C.STORE_F64)
     p = C.particle(shapes.square(120.0, spacing=3.0), 200.3, 120.6, 0.785)
     errs = _compare([(cfg, [p])], 20)[0]
-    assert max(errs.values()) < 1e-11, errs
+    print({k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-12, errs
     cfg32 = dict(cfg, storage=C.STORE_F32)
     other = (C.couette_config(96, 48, storage=C.STORE_F32), [C.particle(shapes.circle(10.0), 40.0, 23.4, 0.0)])
     _, g = run_gpu([other, (cfg32, [p])], 20)
@@ -239,3 +252,28 @@ def test_unstable_run_is_reported_at_the_oracle_step():
     o.add_particle(p)
     with pytest.raises(FloatingPointError, match="step 2"):
         o.step(100)
+
+
+def test_closed_box_sedimentation_fp64():
+    """A circle settling in a closed box (walls on both axes, the corner
+    closure of reading R23): FP64 parity over 1500 steps at the sedimentation
+    bars (the flow is nearly at rest, see the module docstring)."""
+    cfg = C.base_config(40, 90, tau=0.8, bc_x=1, bc_y=1, gravity=[0.0, -2e-5])
+    p = C.particle(shapes.circle(10.0, n_markers=32), 20.0, 60.0, 0.0, 1.05)
+    errs = _compare([(cfg, [p])], 1500)[0]
+    print({k: f"{v:.1e}" for k, v in errs.items()})
+    for k in ("x", "y", "theta", "u", "v", "omega"):
+        assert errs[k] < 5e-11, (k, errs)
+    for k in ("Fx", "Fy", "M"):
+        assert errs[k] < 1e-9, (k, errs)
+
+
+def test_particle_near_box_corner_fp64():
+    """A particle thrown toward a corner of a closed box: its probe stencils
+    reach the wall column (the particle kernels apply the wall and corner
+    closures to the nodes they pull)."""
+    cfg = C.base_config(36, 30, tau=0.9, bc_x=1, bc_y=1, gravity=[-3e-5, -3e-5])
+    p = C.particle(shapes.circle(8.0, n_markers=26), 7.05, 7.1, 0.0, 1.2, u=-0.04, v=-0.04)
+    errs = _compare([(cfg, [p])], 200)[0]
+    print({k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-11, errs

@@ -64,6 +64,33 @@ def test_side_walls_bitwise():
     assert np.array_equal(a, b)
 
 
+def _bump(nx, ny, amp=0.01):
+    f = np.zeros((9, ny, nx))
+    for y in range(ny):
+        for x in range(nx):
+            dx, dy = x - 0.37 * nx, y - 0.61 * ny
+            f[:, y, x] = oracle.equilibrium(1.0 + amp * np.exp(-(dx * dx + dy * dy) / 6.0), 0.0, 0.0)
+    return f
+
+
+@pytest.mark.parametrize("nx,ny", [(23, 17), (3, 3), (70, 4)])
+def test_closed_box_bitwise(nx, ny):
+    """Walls on both axes: the corner closure of reading R23 (each corner
+    takes its diagonal interior neighbour's density) matches the oracle bit
+    for bit."""
+    cfg = C.base_config(nx, ny, tau=0.8, bc_x=1, bc_y=1)
+    a, b = _lattice_pair(cfg, 60, _bump(nx, ny))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage,tol", [(C.STORE_F32, 2e-8), (C.STORE_F16S, 3e-5)])
+def test_closed_box_reduced_forms(storage, tol):
+    cfg = C.base_config(31, 22, tau=0.8, bc_x=1, bc_y=1)
+    f = _bump(31, 22)
+    a, b = _lattice_pair(cfg, 60, f, storage=storage)
+    assert np.abs(a - b).max() < tol
+
+
 @pytest.mark.parametrize("tile_w,npt,pers,ov", [(64, 1, 0, 0), (128, 2, 0, 0), (256, 4, 0, 0), (64, 4, 7, 0),
                                                 (256, 1, 3, 0), (64, 1, 0, 1), (64, 2, 0, 1), (64, 4, 0, 1)])
 def test_launch_shapes_do_not_change_results(tile_w, npt, pers, ov):
