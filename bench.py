@@ -5,18 +5,25 @@ A step is one pass of the whole hot path: immersed-boundary force and
 spreading, the lattice pass (streaming, walls, forced collision) and the
 surface-stress / rigid-body update, for every channel of the workload.
 
-Default workload: the Re = 20 Couette channel (400 x 100 lattice, periodic
-in x, walls moving at -U/+U, one neutrally buoyant ellipse of aspect ratio 2
-and major axis 25 with 64 markers), FP32 storage.  Other workloads of the
-same family: --workload sedimentation | ensemble | large | adjoint.
+Default workload: the batched ensemble of 256 independent Re = 20 Couette
+channels of uneven size (H in {64, 96, 128, 192, 256}, L = 4H, 27.76 M nodes,
+one particle of one of the five shape families each), FP32 storage, one
+handle replayed from HIP graphs.  Other workloads of the same family:
+--workload couette | sedimentation | large | huge | adjoint.
 
-Prints one JSON line with the metric, a roofline object for the dominant
-kernel (HIP-event timing of that kernel alone on the library's stream) and a
-CPU baseline from the FP64 oracle run on a bounded sample of the workload.
+Prints one JSON line: the metric over exactly --steps timed steps, the median
+of five more timed repeats, a roofline object for the lattice pass (HIP-event
+timing of that kernel alone on the library's stream) and for the whole step,
+the library's own copy-kernel ceiling, comparison variants (the plain
+single-channel and per-channel forms, FP16S storage, a domain too large for
+the Infinity Cache), the adjoint/forward cost, the trajectory errors of the
+reduced forms at their workloads' full lengths, and a CPU baseline from the
+FP64 oracle on a bounded sample of the workload.
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -29,7 +36,19 @@ METRIC = "MLUPS fused D2Q9+MLS-IBM step (plain vs batched/FP16); adjoint/forward
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {0: 144, 1: 72, 2: 36}  # 9 reads + 9 writes per node
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
+STORE_NAME = ["F64", "F32", "F16S"]
 DTYPE = {0: "f64", 1: "f32", 2: "f32 (f16 storage)"}
+REPEATS = 5
+
+# Launch shapes picked by the autotuner (paper_1606_01805_amd/tune.py) per
+# workload and storage form.
+WORKLOAD_TUNING = {"couette": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1),
+                   "ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0)}
+VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0),
+                  "large": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
+                  "large16": dict(tile_w=64, rows_per_thread=4, xcd_remap=1),
+                  "huge": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
+                  "huge16": dict(tile_w=64, rows_per_thread=4, xcd_remap=1)}
 
 
 def parse():
@@ -37,16 +56,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="couette",
-                    choices=["couette", "sedimentation", "ensemble", "large", "adjoint"])
+    ap.add_argument("--workload", default="ensemble",
+                    choices=["ensemble", "couette", "sedimentation", "large", "huge", "adjoint"])
     ap.add_argument("--storage", default=None, choices=list(STORAGE))
     ap.add_argument("--plain", action="store_true",
                     help="ensemble only: one handle per channel (per-channel launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain device copy of 256 MiB (counter calibration)")
+    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-channels", type=int, default=8)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--repeats", type=int, default=REPEATS)
     ap.add_argument("--tile-w", type=int, default=None)
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--persistent", type=int, default=None)
@@ -56,76 +75,65 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the lattice launch shape with the project autotuner first")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the batched / plain / FP16S comparison runs")
+                    help="skip the comparison workloads, the adjoint leg and the trajectory errors")
     return ap.parse_args()
 
 
 def default_steps(name):
-    return {"couette": (50000, 2000), "sedimentation": (2000, 200), "ensemble": (1000, 100),
-            "large": (2000, 200), "adjoint": (2000, 200)}[name]
+    return {"ensemble": (1000, 100), "couette": (20000, 2000), "sedimentation": (2000, 200),
+            "large": (2000, 200), "huge": (200, 20), "adjoint": (2000, 200)}[name]
 
 
-def cpu_baseline(wl, seconds):
-    """The FP64 oracle as it stands, one host thread, on the first channel of
-    the workload for as many steps as fit in about `seconds`.  Its trajectory
-    then serves as the reference for the trajectory error of the reduced
-    storage forms, run on the GPU for the same steps from the same state."""
+def make_workload(name, storage):
+    from workloads import configs as C
+
+    if name == "huge":
+        return C.large(storage=storage, nx=8192, ny=4096)
+    return C.BY_NAME[name](storage=storage)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(wl, n_channels, steps):
+    """The FP64 oracle as it stands on the first n_channels channels of the
+    workload for `steps` steps: once on one host thread (the form the parity
+    tests use), once with its node loops on every host thread available to
+    this process (OMP_NUM_THREADS if set, else the CPU count).  The
+    immersed-boundary and particle stages of the oracle stay serial."""
     import oracle
 
-    cfg, parts = wl.channels[0]
-    cfg = dict(cfg, storage=0)
-    o = oracle.Oracle(cfg)
-    for p in parts:
-        o.add_particle(p)
-    nodes = cfg["nx"] * cfg["ny"]
-    t0 = time.perf_counter()
-    first = o.step(2, record=True)
-    per = (time.perf_counter() - t0) / 2
-    n = max(2, int(seconds / max(per, 1e-9)))
-    t0 = time.perf_counter()
-    rest = o.step(n, record=True)
-    dt = time.perf_counter() - t0
-    out = {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-           "sample": f"{n} steps of channel 0 ({cfg['nx']}x{cfg['ny']}, {len(parts)} particle(s)) "
-                     f"in FP64 on one host thread, {dt:.1f} s"}
-    if parts:
-        ref = np.concatenate([first, rest], 0)
-        out["trajectory_error"] = trajectory_errors(cfg, parts, ref)
+    chans = wl.channels[:n_channels]
+    nodes = sum(c["nx"] * c["ny"] for c, _ in chans)
+    nparts = sum(len(p) for _, p in chans)
+    avail = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", avail) or avail)
+    runs = {}
+    for th in (1, threads):
+        t0 = time.perf_counter()
+        for cfg, parts in chans:
+            o = oracle.Oracle(dict(cfg, storage=0))
+            o.set_threads(th)
+            for p in parts:
+                o.add_particle(p)
+            o.step(steps, record=False)
+        runs[th] = time.perf_counter() - t0
+    out = {"value": nodes * steps / runs[threads] / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} steps of the first {len(chans)} channels ({nodes} nodes, {nparts} particles) in "
+                     f"FP64, node loops on {threads} threads: {runs[threads]:.1f} s",
+           "single_thread": {"value": nodes * steps / runs[1] / 1e6, "unit": "MLUPS", "cores": 1,
+                             "seconds": runs[1]},
+           "host": {"cpu_model": host_cpu(), "os_cpu_count": avail, "threads_used": threads}}
     return out
-
-
-def trajectory_errors(cfg, parts, ref):
-    """Largest deviation from the oracle trajectory ref [n, particles, 10]
-    over the run, per storage form: positions over the wall gap (or the
-    channel height), angle in radians, angular velocity over the wall shear
-    rate (or over the largest |omega| of the reference when the walls are at
-    rest)."""
-    import torch
-
-    from paper_1606_01805_amd import Solver
-
-    steps = ref.shape[0]
-    gap = cfg["ny"] - 1
-    shear = abs(cfg["u_wall"][3][0] - cfg["u_wall"][2][0]) / gap
-    om_scale = shear if shear > 0 else max(np.abs(ref[..., 5]).max(), 1e-300)
-    res = {"steps": steps, "metrics": "pos/(NY-1), theta [rad], omega/shear rate"}
-    for name, st in (("F32", 1), ("F16S", 2), ("F64", 0)):
-        s = Solver([(dict(cfg, storage=st), parts)])
-        g = s.step(steps, record=True)
-        torch.cuda.synchronize()
-        s.close()
-        res[name] = {"pos": float(np.abs(g[..., 0:2] - ref[..., 0:2]).max() / gap),
-                     "theta": float(np.abs(g[..., 2] - ref[..., 2]).max()),
-                     "omega": float(np.abs(g[..., 5] - ref[..., 5]).max() / om_scale)}
-    return res
-
-
-# Launch shapes picked by the autotuner: the main workload's default (used
-# when no launch flag is given) and the comparison workloads.
-WORKLOAD_TUNING = {"couette": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1)}
-VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0),
-                  "large": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
-                  "large16": dict(tile_w=64, rows_per_thread=4, xcd_remap=1)}
 
 
 def kernel_source_sha():
@@ -140,7 +148,7 @@ def kernel_source_sha():
 def measured_traffic(key):
     """HBM bytes per lattice launch from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain
-    256 MiB copy), or None when the kernel source changed since."""
+    copy), or None when the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(path))
@@ -152,51 +160,79 @@ def measured_traffic(key):
     return e["bytes_per_launch"]
 
 
-def roofline(us_lattice, nodes, storage, traffic_key=None, tuning=None):
+def roofline(us_lattice, nodes, storage, traffic_key=None, tuning=None, ms_step=None):
     b = nodes * BYTES_PER_LUP[storage]
     ach = b / (us_lattice * 1e-6) / 1e9
-    # with the combined launch the lattice pass is timed as that kernel
-    # without its particle workgroups
     name = ("lattice_traction_kernel (lattice workgroups only)" if tuning and tuning.get("overlap")
             else "lattice_kernel")
-    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "bytes_per_launch": b, "us_per_launch": us_lattice,
-            "timing": "HIP events on the library stream around back-to-back launches of the "
-                      "kernel alone, right after the timed steps (lbm_time_kernels)"}
+    out = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+           "traffic": measured_traffic(traffic_key) if traffic_key else None,
+           "bytes_per_launch": b, "us_per_launch": us_lattice,
+           "timing": "HIP events on the library stream around back-to-back launches of the "
+                     "kernel alone on a step's tile lists, right after the timed steps (lbm_time_kernels)"}
+    if ms_step:
+        step_gbs = b / (ms_step * 1e-3) / 1e9
+        out["whole_step"] = {"achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS, "ms_per_step": ms_step,
+                             "note": "the step's algorithmic bytes over the median step time (all kernels)"}
+    return out
 
 
-def run_variant(name, storage, steps, warm, plain=False, tuning=None):
-    """MLUPS of one comparison workload plus its lattice-kernel roofline."""
+def timed_steps(solvers, steps):
     import torch
 
-    from paper_1606_01805_amd import Solver
-    from workloads import configs as C
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps, record=False)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
-    wl = C.BY_NAME[name](storage=storage)
+
+def copy_ceiling(nbytes=1 << 30, reps=20):
+    """GB/s of the library's hand-written copy kernel (read + write) over two
+    buffers of nbytes: the practical ceiling of an HBM-bound pass."""
+    import ctypes
+
+    import torch
+
+    from paper_1606_01805_amd import _lib
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    g = ctypes.c_double()
+    st = torch.cuda.current_stream().cuda_stream
+    _lib.check(_lib.lib().lbm_measure_copy(b.data_ptr(), a.data_ptr(), nbytes, reps, ctypes.c_void_p(st),
+                                           ctypes.byref(g)))
+    del a, b
+    torch.cuda.synchronize()
+    return {"GB/s": g.value, "frac_of_peak": g.value / HBM_PEAK_GBS,
+            "what": f"lbm_measure_copy: 16-byte loads/stores, {nbytes >> 20} MiB read + written per launch, "
+                    f"average of {reps} launches"}
+
+
+def run_variant(name, storage, steps, warm, plain=False, tuning=None, traffic_key=None):
+    """MLUPS of one comparison workload plus its lattice-kernel roofline."""
+    from paper_1606_01805_amd import Solver
+
+    wl = make_workload(name, storage)
     solvers = ([Solver([ch], tuning=tuning) for ch in wl.channels] if plain
                else [Solver(wl.channels, tuning=tuning)])
     for sv in solvers:
         sv.step(warm, record=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for sv in solvers:
-        sv.step(steps, record=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out = {"workload": wl.name, "storage": ["F64", "F32", "F16S"][storage],
+    dt = timed_steps(solvers, steps)
+    out = {"workload": wl.name, "nodes": wl.nodes, "storage": STORE_NAME[storage],
            "launch": "plain (one handle per channel)" if plain else "single handle, HIP graph",
-           "steps": steps, "MLUPS": wl.nodes * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3}
+           "steps": steps, "MLUPS": wl.nodes * steps / dt / 1e6, "us_per_step": dt / steps * 1e6}
     if not plain:
         s0 = solvers[0]
         s0.checkpoint_save(7)
-        us = s0.time_kernels(20)
+        us = s0.time_kernels(200 if wl.nodes < 1_000_000 else 20)
         s0.checkpoint_restore(7)
         out["kernel_us"] = dict(zip(["ibm_force", "lattice", "traction"], [float(v) for v in us]))
-        key = {("ensemble", 1): "ensemble_f32", ("large", 1): "large_f32", ("large", 2): "large_f16s"}.get((name, storage))
         out["tuning"] = s0.tuning()
-        out["roofline"] = roofline(float(us[1]), wl.nodes, storage, key, out["tuning"])
+        out["roofline"] = roofline(float(us[1]), wl.nodes, storage, traffic_key, out["tuning"], dt / steps * 1e3)
     for sv in solvers:
         sv.close()
     return out
@@ -239,7 +275,7 @@ def adjoint_leg(storage=1, steps=2000, seg=100):
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     s.close()
-    return {"workload": wl.name, "storage": ["F64", "F32", "F16S"][storage], "steps": steps, "segment": seg,
+    return {"workload": wl.name, "storage": STORE_NAME[storage], "steps": steps, "segment": seg,
             "forward_us_per_step": t_plain / steps * 1e6,
             "forward_checkpointed_us_per_step": t_fwd / steps * 1e6,
             "adjoint_us_per_step": t_adj / steps * 1e6,
@@ -247,22 +283,56 @@ def adjoint_leg(storage=1, steps=2000, seg=100):
             "note": "adjoint time includes recomputing each segment from its checkpoint"}
 
 
+def trajectory_errors():
+    """Trajectory error of FP32 and FP16S storage against the FP64 oracle
+    trajectories of tests/golden (written by make_trajectory_golden.py, oracle
+    only) over the workloads' full lengths: positions over the wall gap, angle
+    in radians, angular velocity over the wall shear rate."""
+    from paper_1606_01805_amd import Solver
+    from workloads import configs as C
+
+    out = {"metrics": "pos/(NY-1), theta [rad], omega/shear rate; max over kept steps and particles"}
+    cases = [("couette_400x100_50k_fp64.npz", "couette", {1: WORKLOAD_TUNING["couette"], 2: WORKLOAD_TUNING["couette"]}),
+             ("large_4096x1024_10k_fp64.npz", "large", {1: VARIANT_TUNING["large"], 2: VARIANT_TUNING["large16"]})]
+    for fname, name, tun in cases:
+        path = os.path.join(ROOT, "tests", "golden", fname)
+        if not os.path.exists(path):
+            continue
+        g = np.load(path)
+        steps, ref, total = g["steps"], g["rec"], int(g["total_steps"])
+        res = {"steps": total}
+        for st in (1, 2):
+            wl = C.BY_NAME[name](storage=st)
+            cfg = wl.channels[0][0]
+            s = Solver(wl.channels, tuning=tun[st])
+            tr = s.step(total, record=True)
+            s.close()
+            run = tr[steps - 1][..., [0, 1, 2, 5]]
+            gap = cfg["ny"] - 1
+            shear = abs(cfg["u_wall"][3][0] - cfg["u_wall"][2][0]) / gap
+            res[STORE_NAME[st]] = {"pos": float(np.abs(run[..., 0:2] - ref[..., 0:2]).max() / gap),
+                                   "theta": float(np.abs(run[..., 2] - ref[..., 2]).max()),
+                                   "omega": float(np.abs(run[..., 3] - ref[..., 3]).max() / shear)}
+        out[name] = res
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only: the coupled step has no multi-GPU path",
+        print(json.dumps({"error": "this build runs on one GPU: the benchmark has no multi-GPU path "
+                                   "(the sharding design is described in the design notes)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
     from paper_1606_01805_amd import Solver
-    from workloads import configs as C
 
     steps, warm = default_steps(args.workload)
     steps = args.steps if args.steps is not None else steps
     warm = args.warmup if args.warmup is not None else warm
     storage = STORAGE[args.storage] if args.storage else (0 if args.workload == "sedimentation" else 1)
-    wl = C.BY_NAME[args.workload](storage=storage)
+    wl = make_workload(args.workload, storage)
     tuning = {}
     if args.tile_w:
         tuning["tile_w"] = args.tile_w
@@ -275,14 +345,8 @@ def main():
     if args.overlap is not None:
         tuning["overlap"] = args.overlap
     if not tuning and not args.autotune and not args.plain:
-        tuning = dict(WORKLOAD_TUNING.get(args.workload, {}))
-
-    if args.copy_calibration:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        key = args.workload + ("16" if storage == 2 and args.workload in ("large", "huge") else "")
+        tuning = dict(WORKLOAD_TUNING.get(args.workload, VARIANT_TUNING.get(key, {})))
 
     solvers = ([Solver([ch], tuning=tuning) for ch in wl.channels] if args.plain
                else [Solver(wl.channels, tuning=tuning)])
@@ -294,16 +358,15 @@ def main():
         for s in solvers[1:]:
             s.set_tuning(**best)
         tune_report = {k: v * 1e6 for k, v in res.items()}
+    # warm-up: graphs of both step parities are captured on the first
+    # multi-step call, so no capture falls in the timed region
     for s in solvers:
         s.step(warm, record=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in solvers:
-        s.step(steps, record=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = timed_steps(solvers, steps)
     nodes = wl.nodes
     mlups = nodes * steps / dt / 1e6
+    reps = [timed_steps(solvers, steps) / steps * 1e3 for _ in range(args.repeats)]
+    med = statistics.median(reps) if reps else dt / steps * 1e3
 
     # Per-kernel device time, HIP events around back-to-back launches of each
     # kernel alone on the library's stream (after the timed region).
@@ -312,23 +375,24 @@ def main():
     us = s0.time_kernels(args.kernel_reps)
     s0.checkpoint_restore(7)
     names = ["ibm_force", "lattice", "traction"]
-    k = int(max(range(3), key=lambda i: us[i]))
     nodes0 = sum(c["nx"] * c["ny"] for c in s0.cfgs)
     key = {("couette", 1): "couette_f32", ("ensemble", 1): "ensemble_f32", ("large", 1): "large_f32",
-           ("large", 2): "large_f16s"}.get((args.workload, storage))
-    roof = roofline(float(us[1]), nodes0, storage, key if not args.plain else None, s0.tuning())
+           ("large", 2): "large_f16s", ("huge", 1): "huge_f32", ("huge", 2): "huge_f16s"}.get((args.workload, storage))
+    roof = roofline(float(us[1]), nodes0, storage, key if not args.plain else None, s0.tuning(),
+                    med if not args.plain else None)
+    k = int(max(range(3), key=lambda i: us[i]))
     if k != 1:
-        # the particle kernels (one workgroup per particle) are latency bound;
-        # the lattice pass is the kernel that moves the step's bytes
         roof["dominant_by_time"] = names[k]
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": warm, "ms_per_step": dt / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[storage], "data": "synthetic",
         "config": {"workload": wl.name, "nodes": nodes, "channels": len(wl.channels),
-                   "particles": wl.n_particles, "storage": ["F64", "F32", "F16S"][storage],
+                   "particles": wl.n_particles, "storage": STORE_NAME[storage],
                    "launch": "plain (per channel)" if args.plain else "single handle, HIP graph",
                    "tuning": s0.tuning()},
+        "repeats": {"n": len(reps), "steps_each": steps, "ms_per_step": reps, "median_ms_per_step": med,
+                    "median_MLUPS": nodes / (med * 1e-3) / 1e6},
         "kernel_us": dict(zip(names, [float(v) for v in us])),
         "roofline": roof,
     }
@@ -336,19 +400,27 @@ def main():
         out["autotune_us_per_step"] = tune_report
     for sv in solvers:
         sv.close()
-    if not args.no_variants and args.workload == "couette":
-        # plain vs batched (256 uneven channels) and FP32 vs FP16S storage
+    torch.cuda.synchronize()
+    out["copy_ceiling"] = copy_ceiling()
+    out["roofline"]["frac_of_copy_ceiling"] = roof["achieved"] / out["copy_ceiling"]["GB/s"]
+    if not args.no_variants and args.workload == "ensemble":
+        # plain vs batched, FP32 vs FP16S, a domain that does not fit the
+        # 256 MB Infinity Cache, and the small latency-bound cases
         out["variants"] = [
-            run_variant("ensemble", 1, 300, 30, tuning=VARIANT_TUNING["ensemble"]),
-            run_variant("ensemble", 1, 30, 5, plain=True),
-            run_variant("large", 1, 500, 50, tuning=VARIANT_TUNING["large"]),
-            run_variant("large", 2, 500, 50, tuning=VARIANT_TUNING["large16"]),
+            run_variant("ensemble", 1, 30, 6, plain=True),
+            run_variant("couette", 1, 4000, 400, tuning=WORKLOAD_TUNING["couette"], traffic_key="couette_f32"),
+            run_variant("sedimentation", 0, 2000, 200),
+            run_variant("large", 1, 500, 50, tuning=VARIANT_TUNING["large"], traffic_key="large_f32"),
+            run_variant("large", 2, 500, 50, tuning=VARIANT_TUNING["large16"], traffic_key="large_f16s"),
+            run_variant("huge", 1, 100, 10, tuning=VARIANT_TUNING["huge"], traffic_key="huge_f32"),
+            run_variant("huge", 2, 100, 10, tuning=VARIANT_TUNING["huge16"], traffic_key="huge_f16s"),
         ]
         out["adjoint"] = adjoint_leg()
+        out["trajectory_error"] = trajectory_errors()
     if args.workload == "adjoint":
         out["adjoint"] = adjoint_leg(storage=storage)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_channels, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

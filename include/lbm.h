@@ -288,6 +288,18 @@ int lbm_adjoint_gradients(lbm_handle* h, double* part_out, double* marker_out, d
  * Zou-He closure (zero for the three it reconstructs). */
 int lbm_adjoint_field(lbm_handle* h, int32_t channel, double* out);
 
+/* Bandwidth of a plain device-to-device copy of `bytes` (a positive multiple
+ * of 16) from src to dst (DEVICE pointers, not overlapping, owned by the
+ * caller) with the library's own copy kernel (16-byte nontemporal loads and
+ * stores, 4 per lane, one contiguous 16 KiB block per workgroup of 256
+ * threads): *gbps receives
+ * the read plus written bytes per second, in GB/s, averaged over `reps`
+ * back-to-back launches on hip_stream after one untimed launch (HIP
+ * events).  This is the practical ceiling of the HBM-bound lattice pass.
+ * Errors: LBM_EINVAL (NULL pointer, reps < 1, bad size), LBM_EDEVICE; the
+ * text is in lbm_last_error(NULL). */
+int lbm_measure_copy(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream, double* gbps);
+
 /* Step index the adjoint currently refers to (-1: none in progress). */
 int64_t lbm_adjoint_position(const lbm_handle* h);
 

@@ -74,6 +74,7 @@ def lib():
         L.orc_get_marker_record.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, ctypes.c_int32]
         L.orc_anchor_hash.restype = ctypes.c_uint64
         L.orc_anchor_hash.argtypes = [ctypes.c_void_p]
+        L.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.orc_lattice.argtypes = [_dp, _dp]
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [_dp]
         L.orc_collide_node.argtypes = [_dp] + [ctypes.c_double] * 5 + [_dp, _dp, _dp, _dp]
@@ -213,6 +214,10 @@ class Oracle:
 
     def anchor_hash(self) -> int:
         return int(self._L.orc_anchor_hash(self._h))
+
+    def set_threads(self, n: int):
+        """Threads for the node loops (results do not depend on it)."""
+        self._L.orc_set_threads(self._h, int(n))
 
 
 # ---- stage functions (closed-form tests) ----

@@ -309,6 +309,7 @@ struct orc_sim {
     particle* p;
     uint64_t anchor_hash;
     int steps_done;
+    int threads; /* threads of the node loops (1 unless orc_set_threads) */
 };
 
 static size_t idx(const orc_sim* s, int i, int y, int x) {
@@ -422,6 +423,7 @@ orc_sim* orc_create(const orc_config* cfg) {
     s->rmark = (unsigned char*)calloc(s->n, 1);
     s->pmark = (unsigned char*)calloc(s->n, 1);
     s->anchor_hash = 1469598103934665603ULL;
+    s->threads = 1;
     /* Initial populations: f^eq(1, u0) (Sec. 3.1: planar Couette start), then
      * the wall reconstruction so f^0 satisfies the boundary conditions. */
     double feq[9];
@@ -562,6 +564,8 @@ int orc_get_marker_record(const orc_sim* s, int32_t p, double* out, int32_t cap)
 
 uint64_t orc_anchor_hash(const orc_sim* s) { return s->anchor_hash; }
 
+void orc_set_threads(orc_sim* s, int32_t n) { s->threads = n < 1 ? 1 : n; }
+
 /* Running hash of every MLS stencil anchor used (markers and probes).  The
  * anchors are piecewise constant in the particle state, so two runs with equal
  * hashes differ only through the smooth part of the step map. */
@@ -649,7 +653,10 @@ static int one_step(orc_sim* s, double* rec_out) {
     int bad = 0;
 
     /* Moments of f^n, Eqs. (6), (7): rho and j* = sum f e + g/2 (the IB
-     * force is not known yet, reading R2). */
+     * force is not known yet, reading R2).  The node loops of this function
+     * may run their rows on several threads (orc_set_threads): every node is
+     * computed on its own, so the results do not depend on the thread count. */
+#pragma omp parallel for reduction(| : bad) num_threads(s->threads)
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             double r = 0.0, jx = 0.0, jy = 0.0;
@@ -749,8 +756,9 @@ static int one_step(orc_sim* s, double* rec_out) {
     }
 
     /* Forced collision of every node, Eqs. (4), (5) (readings R2, R3). */
-    double fl[9], fo[9];
+#pragma omp parallel for num_threads(s->threads)
     for (int y = 0; y < ny; ++y) {
+        double fl[9], fo[9];
         for (int x = 0; x < nx; ++x) {
             size_t n = (size_t)y * nx + x;
             for (int i = 0; i < Q; ++i) fl[i] = s->f[idx(s, i, y, x)];
@@ -806,6 +814,7 @@ static int one_step(orc_sim* s, double* rec_out) {
      * the Zou-He reconstruction. */
     for (int i = 0; i < Q; ++i) {
         int ex = (int)E[i][0], ey = (int)E[i][1];
+#pragma omp parallel for num_threads(s->threads)
         for (int y = 0; y < ny; ++y) {
             int ys = y - ey;
             if (c->bc_y == ORC_PERIODIC) {

@@ -86,6 +86,10 @@ void orc_get_last_velocity(const orc_sim* s, double* ux, double* uy);
 int orc_get_marker_record(const orc_sim* s, int32_t p, double* out, int32_t cap);
 /* Hash of all stencil anchors used so far (for finite-difference validity). */
 uint64_t orc_anchor_hash(const orc_sim* s);
+/* Threads that the node loops (moments, collision, streaming) may use; the
+ * immersed-boundary and particle stages stay serial.  Results do not depend
+ * on it (every node is computed on its own).  Default 1. */
+void orc_set_threads(orc_sim* s, int32_t n);
 
 /* ---- stage functions, exposed for the closed-form tests ---- */
 void orc_lattice(double e[9][2], double w[9]);

@@ -72,6 +72,8 @@ SIGNATURES = {
     "lbm_adjoint_segment": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbm_adjoint_gradients": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "lbm_adjoint_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
+    "lbm_measure_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                        ctypes.c_void_p, _dp]),
     "lbm_adjoint_position": (ctypes.c_int64, [ctypes.c_void_p]),
     "lbm_steps_done": (ctypes.c_int64, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),

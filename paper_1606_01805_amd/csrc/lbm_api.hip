@@ -1133,6 +1133,28 @@ extern "C" int lbm_adjoint_field(lbm_handle* h, int32_t ch, double* out) {
     return LBM_OK;
 }
 
+extern "C" int lbm_measure_copy(void* dst, const void* src, size_t bytes, int32_t reps, void* stream,
+                                double* gbps) {
+    if (!dst || !src || !gbps || reps < 1 || bytes == 0 || bytes % 16 != 0)
+        FAIL((lbm_handle*)nullptr, LBM_EINVAL, "lbm_measure_copy: NULL pointer, reps < 1 or bytes not a positive multiple of 16");
+    hipStream_t s = (hipStream_t)stream;
+    const long long n16 = (long long)(bytes / 16);
+    hipEvent_t e0, e1;
+    HIPCHK((lbm_handle*)nullptr, hipEventCreate(&e0));
+    HIPCHK((lbm_handle*)nullptr, hipEventCreate(&e1));
+    HIPCHK((lbm_handle*)nullptr, launch_copy(dst, src, n16, s));  // warm
+    HIPCHK((lbm_handle*)nullptr, hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIPCHK((lbm_handle*)nullptr, launch_copy(dst, src, n16, s));
+    HIPCHK((lbm_handle*)nullptr, hipEventRecord(e1, s));
+    HIPCHK((lbm_handle*)nullptr, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK((lbm_handle*)nullptr, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return LBM_OK;
+}
+
 extern "C" int64_t lbm_adjoint_position(const lbm_handle* h) { return h ? h->adj_pos : -1; }
 
 extern "C" int64_t lbm_steps_done(const lbm_handle* h) { return h ? h->steps : -1; }
