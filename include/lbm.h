@@ -206,6 +206,19 @@ int lbm_get_particles(const lbm_handle* h, double* out, int32_t cap, int32_t* n_
  * channel, each [ny][nx] (host); any pointer may be NULL. */
 int lbm_get_fields(lbm_handle* h, int32_t channel, double* rho, double* ux, double* uy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or diagnostic loops, harnesses that forbid
+ * hipMalloc): lbm_get_fields without any allocation.  The fields are staged
+ * in a fixed device array of the library (3 x 2^18 doubles, 6 MiB, on each
+ * GPU the library runs on, held until the process ends), so the channel may
+ * have at most 262 144 nodes (nx * ny), else LBM_ECAPACITY and nothing is
+ * written.  Results are those of lbm_get_fields, bit for bit.  Calls on one
+ * GPU share that array: calls that overlap in time on one GPU (from several
+ * host threads, or handles on different streams) race; calls from one host
+ * thread are safe, as each returns after its copies complete.  Errors:
+ * LBM_EINVAL (NULL handle, bad channel), LBM_ECAPACITY, LBM_EDEVICE. */
+int lbm_get_fields_noalloc(lbm_handle* h, int32_t channel, double* rho, double* ux, double* uy);
+
 /* Current populations f^n (after streaming and walls) of a channel, converted
  * to FP64, [9][ny][nx] (host). */
 int lbm_get_populations(lbm_handle* h, int32_t channel, double* f);

@@ -61,6 +61,7 @@ SIGNATURES = {
     "lbm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_get_particles": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_get_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, _dp]),
+    "lbm_get_fields_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, _dp]),
     "lbm_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_checkpoint_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),

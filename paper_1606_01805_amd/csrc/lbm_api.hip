@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,16 @@
 #include "lbm_internal.h"
 
 using namespace lbmk;
+
+// Staging of lbm_get_fields_noalloc: the density and two velocity fields of
+// a channel of at most kScratchNodes nodes, in a fixed device array (6 MiB
+// on every GPU the library runs on, held until the process ends).  Host code
+// never passes `scratch` itself to a kernel or copy (in host code the name is
+// a host-side stand-in, not the device address): it uses the address
+// hipGetSymbolAddress gives for the current device, looked up once per
+// device by lbm_init.
+constexpr int kScratchNodes = 1 << 18;
+static __device__ __align__(256) double scratch[3 * kScratchNodes];
 
 namespace {
 
@@ -40,6 +51,31 @@ struct Checkpoint {
 };
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// The device addresses of `scratch`, one per GPU, looked up by lbm_init.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up on the
+// first call for that device), or NULL with *err set.
+double* scratch_for_current_device(hipError_t* err) {
+    int dev = -1;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -104,6 +140,7 @@ struct lbm_handle {
     size_t gwall_n = 0;
     long long adj_pos = -1;        // step of the state the adjoint currently refers to
     bool adj_first = false;
+    double* scratch = nullptr;     // this device's address of `scratch` (lbm_get_fields_noalloc)
     std::string err;
 };
 
@@ -312,6 +349,14 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
     }
     lbm_handle* h = new (std::nothrow) lbm_handle();
     if (!h) FAIL((lbm_handle*)nullptr, LBM_ENOMEM, "out of host memory");
+    {
+        hipError_t e = hipSuccess;
+        h->scratch = scratch_for_current_device(&e);
+        if (!h->scratch) {
+            delete h;
+            FAIL((lbm_handle*)nullptr, LBM_EDEVICE, "address of the staging array: %s", hipGetErrorString(e));
+        }
+    }
     h->cfg.assign(cfg, cfg + n);
     h->store = cfg[0].storage;
     h->elem = elem_size(h->store);
@@ -691,6 +736,23 @@ extern "C" int lbm_get_fields(lbm_handle* h, int32_t ch, double* rho, double* ux
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(d);
     HIPCHK(h, e);
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_fields_noalloc(lbm_handle* h, int32_t ch, double* rho, double* ux, double* uy) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (ch < 0 || ch >= (int)h->cfg.size()) FAIL(h, LBM_EINVAL, "bad channel");
+    const long long n = (long long)h->cfg[ch].nx * h->cfg[ch].ny;
+    if (n > kScratchNodes)
+        FAIL(h, LBM_ECAPACITY, "channel %d has %lld nodes; lbm_get_fields_noalloc stages at most %d (use lbm_get_fields)",
+             ch, n, kScratchNodes);
+    double* d = h->scratch;  // this device's staging array, no allocation
+    StepArgs a = make_args(h, h->cur);
+    HIPCHK(h, launch_fields(h->store, a, ch, h->cfg[ch].nx, h->cfg[ch].ny, nullptr, d, d + n, d + 2 * n, h->stream));
+    double* outs[3] = {rho, ux, uy};
+    for (int k = 0; k < 3; ++k)
+        if (outs[k]) HIPCHK(h, hipMemcpyAsync(outs[k], d + k * n, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
 
