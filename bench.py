@@ -43,12 +43,12 @@ REPEATS = 5
 # Launch shapes picked by the autotuner (paper_1606_01805_amd/tune.py) per
 # workload and storage form.
 WORKLOAD_TUNING = {"couette": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1),
-                   "ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0)}
-VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=2, xcd_remap=0),
+                   "ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1)}
+VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1),
                   "large": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
-                  "large16": dict(tile_w=64, rows_per_thread=4, xcd_remap=1),
-                  "huge": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
-                  "huge16": dict(tile_w=64, rows_per_thread=4, xcd_remap=1)}
+                  "large16": dict(tile_w=256, rows_per_thread=1, xcd_remap=1, vec=1),
+                  "huge": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1),
+                  "huge16": dict(tile_w=512, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1)}
 
 
 def parse():
@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--overlap", type=int, default=None,
                     help="1: lattice pass and surface stress in one launch (needs --tile-w 64)")
+    ap.add_argument("--vec", type=int, default=None,
+                    help="1: vector form of the lattice pass (tile_w / 64 nodes per lane)")
+    ap.add_argument("--nt-store", type=int, default=None,
+                    help="1: nontemporal stores in the vector form")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the lattice launch shape with the project autotuner first")
     ap.add_argument("--no-variants", action="store_true",
@@ -344,6 +348,10 @@ def main():
         tuning["xcd_remap"] = args.xcd_remap
     if args.overlap is not None:
         tuning["overlap"] = args.overlap
+    if args.vec is not None:
+        tuning["vec"] = args.vec
+    if args.nt_store is not None:
+        tuning["nt_store"] = args.nt_store
     if not tuning and not args.autotune and not args.plain:
         key = args.workload + ("16" if storage == 2 and args.workload in ("large", "huge") else "")
         tuning = dict(WORKLOAD_TUNING.get(args.workload, VARIANT_TUNING.get(key, {})))

@@ -147,6 +147,19 @@ typedef struct lbm_tuning {
                                 64 x 9*rows_per_thread nodes.  Needs
                                 tile_w = 64 and persistent_wgs = 0 (else
                                 LBM_EINVAL); results are bitwise those of 0 */
+    int32_t vec;             /* 1: vector form of the lattice pass: each lane
+                                takes nv = tile_w / 64 consecutive nodes of a
+                                row and moves each population plane of them
+                                with one load and one store of nv elements
+                                (at most 16 bytes: nv <= 2 in FP64, 4 in
+                                FP32, 8 in F16S; tile_w 512 is allowed for
+                                F16S); tiles of tile_w x 4 * rows_per_thread
+                                nodes, rows_per_thread 1 or 2, overlap = 0.
+                                Results are bitwise those of vec = 0 */
+    int32_t nt_store;        /* 1 (needs vec = 1): the lattice pass stores
+                                nontemporally, bypassing the caches; faster
+                                when the two population buffers exceed the
+                                256 MB Infinity Cache, slower when they fit */
 } lbm_tuning;
 
 typedef struct lbm_handle lbm_handle;
@@ -173,7 +186,7 @@ int lbm_init(const lbm_channel_config* cfg, int32_t n_channels, void* hip_stream
 /* Add a particle to `channel` before the first lbm_step (or after lbm_reset).
  * The marker arrays are copied.  The history of the
  * BDF2 scheme starts equal to the initial state.
- * Errors: LBM_EINVAL (n_markers < 3, non-unit normal, non-finite or
+ * Errors: LBM_EINVAL (n_markers < 3 or > 2048, non-unit normal, non-finite or
  * non-positive value, body closer than 3 nodes to a wall, body wider than
  * the channel), LBM_ESTATE (after the first step), LBM_ECAPACITY (body too
  * large for the per-particle force patch). */

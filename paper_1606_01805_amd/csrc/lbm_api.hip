@@ -91,7 +91,7 @@ struct lbm_handle {
     ChanDev* dchan = nullptr;
     std::vector<TileDev> htiles;
     TileDev* dtiles = nullptr;
-    lbm_tuning tune{256, 1, 0, 1, 1, 0};
+    lbm_tuning tune{256, 1, 0, 1, 1, 0, 0, 0};
     bool tiles_dirty = true;
     std::vector<PartHost> parts;
     std::vector<int> dev_of_user;  // user particle id -> device index
@@ -232,6 +232,7 @@ extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) 
 // (256 / tile_w) * rows rows; the combined lattice / surface-stress launch
 // runs 64-wide tiles in workgroups of the particle kernel's size (9 waves).
 static int tile_height(const lbm_tuning& t) {
+    if (t.vec) return 4 * t.rows_per_thread;  // one wave per rows_per_thread rows
     return t.overlap ? kIbmThreads / 64 * t.rows_per_thread : (256 / t.tile_w) * t.rows_per_thread;
 }
 
@@ -251,6 +252,7 @@ static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     a.nparts = h->nparts;
     a.persistent = h->tune.persistent_wgs;
     a.xcd_remap = h->tune.xcd_remap;
+    a.nt_store = h->tune.nt_store;
     a.xi = h->dxi;
     a.nrm = h->dnrm;
     a.ds = h->dds;
@@ -585,7 +587,7 @@ static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
     if (h->tune.overlap) {
         HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
     } else {
-        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->tune.vec, h->stream));
         HIPCHK(h, launch_traction(h->store, a, h->stream));
     }
     return LBM_OK;
@@ -850,7 +852,19 @@ extern "C" int lbm_reset(lbm_handle* h) {
 
 extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
     if (!h || !t) FAIL(h, LBM_EINVAL, "NULL argument");
-    if (t->tile_w != 64 && t->tile_w != 128 && t->tile_w != 256) FAIL(h, LBM_EINVAL, "tile_w must be 64, 128 or 256");
+    if (t->vec != 0 && t->vec != 1) FAIL(h, LBM_EINVAL, "vec must be 0 or 1");
+    if (t->nt_store != 0 && t->nt_store != 1) FAIL(h, LBM_EINVAL, "nt_store must be 0 or 1");
+    if (t->nt_store && !t->vec) FAIL(h, LBM_EINVAL, "nt_store = 1 needs vec = 1");
+    if (!t->vec && t->tile_w != 64 && t->tile_w != 128 && t->tile_w != 256)
+        FAIL(h, LBM_EINVAL, "tile_w must be 64, 128 or 256");
+    if (t->vec) {
+        // tile_w / 64 nodes per lane, one chunk of at most 16 bytes per plane
+        const int nv = t->tile_w / 64;
+        if (t->tile_w % 64 != 0 || (nv != 1 && nv != 2 && nv != 4 && nv != 8) || nv * (int)h->elem > 16)
+            FAIL(h, LBM_EINVAL, "vec = 1 needs tile_w = 64 * nv with nv in {1, 2, 4, 8} and nv * element size <= 16 bytes");
+        if (t->rows_per_thread > 2) FAIL(h, LBM_EINVAL, "vec = 1 needs rows_per_thread 1 or 2");
+        if (t->overlap) FAIL(h, LBM_EINVAL, "vec = 1 cannot be combined with overlap = 1");
+    }
     if (t->rows_per_thread != 1 && t->rows_per_thread != 2 && t->rows_per_thread != 4)
         FAIL(h, LBM_EINVAL, "rows_per_thread must be 1, 2 or 4");
     if (t->persistent_wgs < 0) FAIL(h, LBM_EINVAL, "persistent_wgs must be >= 0");
@@ -911,7 +925,7 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
                     a.nwork = 0;
                     HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
                 } else {
-                    HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->stream));
+                    HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->tune.vec, h->stream));
                 }
                 h->cur = 1 - h->cur;
             }

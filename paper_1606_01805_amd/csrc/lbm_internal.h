@@ -7,7 +7,7 @@
 namespace lbmk {
 
 constexpr int kMaxCells = 32768;         // force-patch cells of one particle
-constexpr int kMaxMarkers = 1024;        // markers of one particle
+constexpr int kMaxMarkers = 2048;        // markers of one particle
 constexpr int kRecSlots = 1024;          // trajectory ring-buffer depth (steps)
 constexpr int kMaxNeighbours = 8;        // short candidate lists of force patches
 constexpr int kTileList = 8;             // per-tile list: count + 7 particle indices
@@ -66,6 +66,7 @@ struct StepArgs {
     int nparts;
     int persistent;          // lattice pass: 0 = one WG per tile
     int xcd_remap;           // lattice pass: contiguous tile blocks per XCD
+    int nt_store;            // vector lattice pass: nontemporal stores
     const double2* xi;       // marker pool (body frame)
     const double2* nrm;
     const double* ds;
@@ -96,7 +97,8 @@ enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
 hipError_t launch_init(int store, const StepArgs& a, int chan, int init, int nx, int ny,
                        hipStream_t s);
 hipError_t launch_ibm_force(int store, const StepArgs& a, hipStream_t s);
-hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hipStream_t s);
+// vec = 1: the vector form (tile_w / 64 nodes per lane, tile_h = 4 * npt).
+hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, int vec, hipStream_t s);
 hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s);
 // Force patches of particles of several rounds from their partial patches
 // (after launch_ibm_force).

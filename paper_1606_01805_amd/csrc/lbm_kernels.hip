@@ -369,28 +369,24 @@ __global__ __launch_bounds__(256) void patch_sum_kernel(StepArgs a) {
     const int nr = (P.nm + kRound - 1) / kRound;
     const double2* part = a.partial + P.part_off + q;
     const long long cap = P.patch_cap;
-    constexpr int kMaxRounds = (kMaxMarkers + kRound - 1) / kRound;
-    double2 v[kMaxRounds];
-#pragma unroll
-    for (int r = 0; r < kMaxRounds; ++r) v[r] = r < nr ? part[r * cap] : make_double2(0.0, 0.0);
-    double2 acc = v[0];
-#pragma unroll
-    for (int r = 1; r < kMaxRounds; ++r)
-        if (r < nr) {
-            acc.x += v[r].x;
-            acc.y += v[r].y;
-        }
+    double2 acc = part[0];
+    for (int r = 1; r < nr; ++r) {
+        const double2 v = part[r * cap];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
     a.patch[P.patch_off + q] = acc;
 }
 
 // ---------------------------------------------------------------------------
 // Kernel 2: the lattice pass.
 // ---------------------------------------------------------------------------
-// FP64 form, reference expression order.  f holds the pulled populations.
-__device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c,
-                                                  const ChanDev* cm, int x,
-                                                  int y, double f[9], const PatchRef* tab, int nlist,
-                                                  const char* __restrict__ fin, char* __restrict__ fout) {
+// FP64 form, reference expression order.  f holds the pulled populations;
+// out receives the post-collision populations of node (x, y).
+__device__ __forceinline__ void collide_f64(const StepArgs& a, const ChanDev& c,
+                                            const ChanDev* cm, int x,
+                                            int y, double f[9], const PatchRef* tab, int nlist,
+                                            const char* __restrict__ fin, double out[9]) {
     walls_f64(c, *cm, x, y, f);
     corners_f64(fin, c, x, y, f);
     double rho, jx, jy;
@@ -413,7 +409,7 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
         const double feq = wd(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
         const double Fi = pref * wd(i) * ((3.0 * (exi - ux) + 9.0 * eu * exi) * Gx +
                                           (3.0 * (eyi - uy) + 9.0 * eu * eyi) * Gy);
-        at<double>(fout, boff<double>(c, i, y, x)) = f[i] - (f[i] - feq) / tau + Fi;
+        out[i] = f[i] - (f[i] - feq) / tau + Fi;
     }
     if (!(rho > 0.0) || !isfinite(rho)) {
         a.flags[0] = 1;
@@ -421,13 +417,23 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
     }
 }
 
-// Reduced forms: deviations in FP32.  d holds the pulled deviations.
-template <int ST>
-__device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c,
+__device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c,
                                                   const ChanDev* cm, int x,
-                                                  int y, float d[9], const PatchRef* tab, int nlist,
+                                                  int y, double f[9], const PatchRef* tab, int nlist,
                                                   const char* __restrict__ fin, char* __restrict__ fout) {
-    using T = typename Sto<ST>::T;
+    double out[9];
+    collide_f64(a, c, cm, x, y, f, tab, nlist, fin, out);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) at<double>(fout, boff<double>(c, i, y, x)) = out[i];
+}
+
+// Reduced forms: deviations in FP32.  d holds the pulled deviations; out
+// receives the post-collision deviations of node (x, y).
+template <int ST>
+__device__ __forceinline__ void collide_dev(const StepArgs& a, const ChanDev& c,
+                                            const ChanDev* cm, int x,
+                                            int y, float d[9], const PatchRef* tab, int nlist,
+                                            const char* __restrict__ fin, float out[9]) {
     walls_dev(c, *cm, x, y, d);
     corners_dev<ST>(fin, c, x, y, d);
     const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
@@ -458,7 +464,6 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
     // - 1.5 u.u)) and F = pref w ((3 (e - u) + 9 (e.u) e) . G) (Eqs. (4), (5)).
     const float uG = ux * Gx + uy * Gy;
     const float c0 = 1.5f * usq;
-    float out[9];
     out[0] = d[0] + (wf(0) * (drho - rho * c0) - d[0]) * om + pref * wf(0) * (-3.0f * uG);
     auto pair = [&](int i, int j, float eu, float eG) {
         const float C = drho + rho * (4.5f * eu * eu - c0);
@@ -473,12 +478,22 @@ __device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanD
     pair(2, 4, uy, Gy);
     pair(5, 7, ux + uy, Gx + Gy);
     pair(6, 8, uy - ux, Gy - Gx);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) store_dev<ST>(&at<T>(fout, boff<T>(c, i, y, x)), 0, i, out[i], c);
     if (!(rho > 0.0f) || !isfinite(rho)) {
         a.flags[0] = 1;
         atomicMin(&a.flags[1], (int)(*a.dstep - 1));
     }
+}
+
+template <int ST>
+__device__ __forceinline__ void collide_store_dev(const StepArgs& a, const ChanDev& c,
+                                                  const ChanDev* cm, int x,
+                                                  int y, float d[9], const PatchRef* tab, int nlist,
+                                                  const char* __restrict__ fin, char* __restrict__ fout) {
+    using T = typename Sto<ST>::T;
+    float out[9];
+    collide_dev<ST>(a, c, cm, x, y, d, tab, nlist, fin, out);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) store_dev<ST>(&at<T>(fout, boff<T>(c, i, y, x)), 0, i, out[i], c);
 }
 
 // One tile of the lattice pass: lane (lx, ly) of a TW-wide workgroup handles
@@ -562,6 +577,164 @@ __device__ __forceinline__ void lattice_tile(const StepArgs& a, int t, int lx, i
             if (x < c.nx && y < c.ny) collide_store_dev<ST>(a, c, cm, x, y, d[r], s_tab, nlist, fin, fout);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Vector form of the lattice pass: lane l of a wave takes NV consecutive
+// nodes of a row, [x0 + l NV, x0 + (l + 1) NV), so each population plane of
+// a row arrives in one aligned load of NV elements (at most 16 bytes) and
+// leaves in one store, instead of one access per node.  The pull shift
+// along x is taken from the same chunk: a population streaming in from the
+// left (e_x = +1) needs the element before the chunk, one streaming in from
+// the right (e_x = -1) the element after the node's last one, each loaded on
+// its own with the periodic wrap or wall clamp of the per-node pull.  A tile
+// is 64 NV nodes wide and 4 NPT rows high (one wave per NPT rows).  Per
+// node the arithmetic is that of the per-node form, so the results are bit
+// for bit the same.
+// ---------------------------------------------------------------------------
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+template <int B> struct VecOf;
+template <> struct VecOf<2> { using type = unsigned short; };
+template <> struct VecOf<4> { using type = unsigned; };
+template <> struct VecOf<8> { using type = u32x2; };
+template <> struct VecOf<16> { using type = u32x4; };
+
+template <typename T, int NV>
+__device__ __forceinline__ void vload(const char* base, unsigned off, T (&out)[NV]) {
+    using V = typename VecOf<NV * (int)sizeof(T)>::type;
+    const V v = *(const V*)(base + off);
+    __builtin_memcpy(out, &v, sizeof(V));
+}
+
+// NT: a nontemporal store, which does not keep the line in the caches.  It
+// pays where the two population buffers exceed the 256 MB Infinity Cache
+// (the next step's reads miss it anyway) and costs where they fit.
+template <typename T, int NV, bool NT>
+__device__ __forceinline__ void vstore(char* base, unsigned off, const T (&in)[NV]) {
+    using V = typename VecOf<NV * (int)sizeof(T)>::type;
+    V v;
+    __builtin_memcpy(&v, in, sizeof(V));
+    if constexpr (NT) __builtin_nontemporal_store(v, (V*)(base + off));
+    else *(V*)(base + off) = v;
+}
+
+// The NV streamed values of population i for the nodes [xb, xb + NV) of row
+// y (xb < nx, a multiple of NV): source row y - e_y (wrapped or clamped),
+// columns x - e_x.  k: position of the channel's last node nx - 1 in the
+// chunk, or NV - 1 when the chunk ends before it.
+template <typename T, int NV>
+__device__ __forceinline__ void pull_chunk(const char* fin, const ChanDev& c, int i, int xb, int y, int k,
+                                           T (&v)[NV]) {
+    const int ys = pull_coord(y - ey(i), y, c.ny, c.bcy == 0);
+    T A[NV];
+    vload<T, NV>(fin, boff<T>(c, i, ys, xb), A);
+    if (ex(i) == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = A[j];
+    } else if (ex(i) > 0) {
+        // node xb + j takes column xb + j - 1: the element before the chunk first
+        const T B = at<T>(fin, boff<T>(c, i, ys, pull_coord(xb - 1, xb, c.nx, c.bcx == 0)));
+        v[0] = B;
+#pragma unroll
+        for (int j = 1; j < NV; ++j) v[j] = A[j - 1];
+    } else {
+        // node xb + j takes column xb + j + 1; past the chunk, or past the
+        // channel's last node, one element of its own
+        const int xk = xb + k;
+        const T B = at<T>(fin, boff<T>(c, i, ys, pull_coord(xk + 1, xk, c.nx, c.bcx == 0)));
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = j < k ? A[j + 1 < NV ? j + 1 : NV - 1] : B;
+    }
+}
+
+template <int ST, int NV, int NPT, bool NT>
+__device__ __forceinline__ void lattice_vtile(const StepArgs& a, int t, int lane, int wv) {
+    using T = typename Sto<ST>::T;
+    const int* tl_cur = a.tlist + (long long)a.parity * a.ntiles * kTileList;
+    int* tl_next = a.tlist + (long long)(1 - a.parity) * a.ntiles * kTileList;
+    const TileDev* tp = a.tiles + t;
+    const int tx0 = uni(tp->x0), ty0 = uni(tp->y0);
+    const ChanDev* cm = a.chan + uni(tp->chan);
+    const ChanDev c = load_chan(cm);
+    const char* __restrict__ fin = (const char*)a.fin + c.off * (long long)sizeof(T);
+    char* __restrict__ fout = (char*)a.fout + c.off * (long long)sizeof(T);
+    const int xb = tx0 + lane * NV;
+    const bool xin = xb < c.nx;
+    const int xbl = xin ? xb : 0;  // lanes past the channel's edge load column 0 and store nothing
+    const int k = min(c.nx - 1 - xbl, NV - 1);
+    // the tile's particle list, as in the per-node form
+    const int* e = tl_cur + (long long)t * kTileList;
+    const int cnt = uni(e[0]);
+    if (threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
+    int list[kTileList - 1] = {};
+    int nlist = 0;
+    if (cnt > kTileList - 1) {
+        nlist = kTileList;
+    } else {
+        for (int j = 0; j < cnt; ++j) list_insert(list, nlist, uni(e[1 + j]));
+    }
+    __shared__ PatchRef s_tab[kTileList - 1];
+    if (nlist > 0 && nlist < kTileList) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kTileList - 1; ++j)
+            if (j < nlist && (int)threadIdx.x == j) s_tab[j] = patch_ref(a, a.parts[list[j]]);
+        __syncthreads();
+    }
+    T raw[NPT][9][NV];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int y = ty0 + wv * NPT + r;
+        const int yl = y < c.ny ? y : c.ny - 1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) pull_chunk<T, NV>(fin, c, i, xbl, yl, k, raw[r][i]);
+    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int y = ty0 + wv * NPT + r;
+        if (!xin || y >= c.ny) continue;
+        T res[9][NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int x = xbl + j;
+            if constexpr (ST == ST_F64) {
+                double f[9], o[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = raw[r][i][j];
+                if (x < c.nx) collide_f64(a, c, cm, x, y, f, s_tab, nlist, fin, o);
+                else
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) o[i] = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) res[i][j] = o[i];
+            } else {
+                float d[9], o[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) d[i] = load_dev<ST>(&raw[r][i][j], 0, i, c);
+                if (x < c.nx) collide_dev<ST>(a, c, cm, x, y, d, s_tab, nlist, fin, o);
+                else
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) o[i] = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) store_dev<ST>(&res[i][j], 0, i, o[i], c);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) vstore<T, NV, NT>(fout, boff<T>(c, i, y, xbl), res[i]);
+    }
+}
+
+template <int ST, int NV, int NPT, bool NT>
+__global__ __launch_bounds__(256) void lattice_vkernel(StepArgs a) {
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int stride = a.persistent ? (int)gridDim.x : a.ntiles;
+    int t0 = blockIdx.x;
+    if (a.xcd_remap && !a.persistent) {
+        const int per = (int)gridDim.x / 8;
+        t0 = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    }
+    for (int t = t0; t < a.ntiles; t += stride) lattice_vtile<ST, NV, NPT, NT>(a, t, lane, wv);
 }
 
 template <int ST, int TW, int NPT>
@@ -1028,10 +1201,48 @@ static hipError_t lattice_dispatch(const StepArgs& a, int tile_w, int npt, int g
     return hipGetLastError();
 }
 
-hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, hipStream_t s) {
+template <int ST, int NV>
+static hipError_t vdispatch_npt(const StepArgs& a, int npt, int grid, hipStream_t s) {
+    if (a.nt_store) {
+        if (npt == 1) lattice_vkernel<ST, NV, 1, true><<<grid, 256, 0, s>>>(a);
+        else lattice_vkernel<ST, NV, 2, true><<<grid, 256, 0, s>>>(a);
+    } else {
+        if (npt == 1) lattice_vkernel<ST, NV, 1, false><<<grid, 256, 0, s>>>(a);
+        else lattice_vkernel<ST, NV, 2, false><<<grid, 256, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+// NV = tile_w / 64 nodes per lane; chunks of at most 16 bytes.
+template <int ST>
+static hipError_t lattice_vdispatch(const StepArgs& a, int tile_w, int npt, int grid, hipStream_t s) {
+    constexpr int kMaxNv = 16 / (int)sizeof(typename Sto<ST>::T);
+    const int nv = tile_w / 64;
+    if (nv > kMaxNv || npt > 2) return hipErrorInvalidValue;
+    switch (nv) {
+        case 1: return vdispatch_npt<ST, 1>(a, npt, grid, s);
+        case 2: return vdispatch_npt<ST, 2>(a, npt, grid, s);
+        case 4:
+            if constexpr (kMaxNv >= 4) return vdispatch_npt<ST, 4>(a, npt, grid, s);
+            return hipErrorInvalidValue;
+        case 8:
+            if constexpr (kMaxNv >= 8) return vdispatch_npt<ST, 8>(a, npt, grid, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_lattice(int store, const StepArgs& a, int tile_w, int npt, int vec, hipStream_t s) {
     int grid = a.persistent > 0 ? (a.persistent < a.ntiles ? a.persistent : a.ntiles) : a.ntiles;
     if (a.xcd_remap && a.persistent <= 0) grid = (a.ntiles + 7) / 8 * 8;
     if (grid <= 0) return hipSuccess;
+    if (vec) {
+        switch (store) {
+            case ST_F64: return lattice_vdispatch<ST_F64>(a, tile_w, npt, grid, s);
+            case ST_F32: return lattice_vdispatch<ST_F32>(a, tile_w, npt, grid, s);
+            default: return lattice_vdispatch<ST_F16S>(a, tile_w, npt, grid, s);
+        }
+    }
     switch (store) {
         case ST_F64: return lattice_dispatch<ST_F64>(a, tile_w, npt, grid, s);
         case ST_F32: return lattice_dispatch<ST_F32>(a, tile_w, npt, grid, s);

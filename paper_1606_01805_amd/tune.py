@@ -1,6 +1,6 @@
 """Autotuner of the lattice-pass launch shape (tile width, rows per thread,
 persistent grid, XCD-aware tile order, lattice pass and surface stress
-combined in one launch or not).
+combined in one launch or not, per-node or vector form).
 
 Each candidate is timed on whole steps of the caller's own solver (all three
 kernels, graph-replayed), from a checkpoint that is restored afterwards, so
@@ -31,7 +31,15 @@ def candidates(n_nodes):
     if n_nodes > 4_000_000:  # persistent grids only pay off on big lattices
         for wgs in (1024, 2048, 4096):
             out.append(dict(tile_w=256, rows_per_thread=2, persistent_wgs=wgs, xcd_remap=0, overlap=0))
-    return out
+    # vector form: tile_w / 64 nodes per lane (shapes the storage form does
+    # not allow are skipped when the tuner applies them)
+    for tw in (128, 256, 512):
+        for rows in (1, 2):
+            for remap in (0, 1):
+                for nt in (0, 1):
+                    out.append(dict(tile_w=tw, rows_per_thread=rows, persistent_wgs=0, xcd_remap=remap,
+                                    overlap=0, vec=1, nt_store=nt))
+    return [dict(dict(vec=0, nt_store=0), **c) for c in out]
 
 
 def shape_key(solver):
@@ -68,8 +76,13 @@ def autotune(solver, steps=None, cands=None, cache=DEFAULT_CACHE, slot=6, verbos
     base = solver.tuning()
     solver.checkpoint_save(slot)
     results = {}
+    from ._lib import LBMError
+
     for c in cands:
-        solver.set_tuning(**dict(base, **c))
+        try:
+            solver.set_tuning(**dict(base, **c))
+        except LBMError:
+            continue  # a shape this storage form does not allow
         solver.checkpoint_restore(slot)
         results[json.dumps(c, sort_keys=True)] = time_steps(solver, steps)
         if verbose:

@@ -159,3 +159,20 @@ def test_full_large_domain_sampled_steps(storage, key, tol_pos, tol_f):
     e_pos = np.abs(g[..., 0:2] - r[..., 0:2]).max()
     e_F = np.abs(g[..., 6:8] - r[..., 6:8]).max() / np.abs(r[..., 6:8]).max()
     assert e_pos < tol_pos and e_F < tol_f, (e_pos, e_F)
+
+
+@pytest.mark.parametrize("storage,tw", [(C.STORE_F32, 256), (C.STORE_F16S, 512), (C.STORE_F64, 128)])
+def test_vector_form_coupled_bitwise(storage, tw):
+    """Batched uneven channels with particles: the vector form of the lattice
+    pass gives bitwise the trajectories and populations of the per-node
+    form (the IB force added per node, several particles per tile)."""
+    chans = _small_ensemble(storage)
+    s0, g0 = run_gpu(chans, 120)
+    p0 = [s0.populations(k) for k in range(len(chans))]
+    s0.close()
+    s1, g1 = run_gpu(chans, 120, tuning=dict(vec=1, tile_w=tw, rows_per_thread=2, nt_store=1))
+    p1 = [s1.populations(k) for k in range(len(chans))]
+    s1.close()
+    assert np.array_equal(g0, g1)
+    for a, b in zip(p0, p1):
+        assert np.array_equal(a, b)

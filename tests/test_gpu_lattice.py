@@ -224,3 +224,52 @@ def test_f16s_launch_shapes_with_particles_bitwise():
         assert np.array_equal(tr, tr_ref), tun
         for k in range(2):
             assert np.array_equal(got[k], ref[k]), (tun, k)
+
+
+VEC_SHAPES = {C.STORE_F64: [(64, 1), (128, 1), (128, 2)],
+              C.STORE_F32: [(128, 1), (256, 1), (256, 2)],
+              C.STORE_F16S: [(256, 1), (512, 1), (512, 2), (128, 2)]}
+
+
+@pytest.mark.parametrize("storage", [C.STORE_F64, C.STORE_F32, C.STORE_F16S])
+@pytest.mark.parametrize("case", ["couette_ragged", "side_walls", "periodic_noisy", "box", "tiny", "wide"])
+def test_vector_form_bitwise(storage, case):
+    """The vector form of the lattice pass (vec = 1: tile_w / 64 nodes per
+    lane, one chunk load per population plane, the x shift from the chunk and
+    one extra element) gives bitwise the populations of the per-node form,
+    with periodic wrap, walls on either axis, closed-box corners and ragged
+    widths against every chunk size."""
+    f = None
+    if case == "couette_ragged":
+        cfg = C.couette_config(131, 37)
+    elif case == "side_walls":
+        cfg = C.base_config(67, 40, tau=0.7, bc_x=1, body_force=[0.0, 2e-6],
+                            u_wall=[[0.0, 0.01], [0.0, -0.02], [0, 0], [0, 0]])
+    elif case == "periodic_noisy":
+        cfg = C.base_config(70, 37, tau=0.9, body_force=[1e-5, -2e-6])
+        f = _noisy(37, 70)
+    elif case == "box":
+        cfg = C.base_config(45, 30, tau=0.8, bc_x=1, bc_y=1)
+        f = _bump(45, 30, cfg=cfg)
+    elif case == "tiny":
+        cfg = C.base_config(3, 3, tau=0.9)
+        f = _noisy(3, 3)
+    else:
+        cfg = C.couette_config(1100, 9)  # several vector tiles per row, ragged at the end
+    ref, _ = _lattice_pair(cfg, 30, f, storage=storage)
+    for k, (tw, rows) in enumerate(VEC_SHAPES[storage]):
+        got, _ = _lattice_pair(cfg, 30, f, storage=storage,
+                               tuning=dict(vec=1, tile_w=tw, rows_per_thread=rows, xcd_remap=tw % 256 == 0,
+                                           nt_store=k % 2))
+        assert np.array_equal(got, ref), (tw, rows)
+
+
+def test_vector_form_rejects_bad_shapes():
+    from paper_1606_01805_amd import LBMError, Solver
+
+    s = Solver([(C.couette_config(100, 20), [])], storage=C.STORE_F32)
+    for bad in (dict(vec=1, tile_w=512), dict(vec=1, tile_w=256, rows_per_thread=4),
+                dict(vec=1, tile_w=64, overlap=1), dict(vec=2), dict(vec=0, nt_store=1)):
+        with pytest.raises(LBMError, match="EINVAL"):
+            s.set_tuning(**bad)
+    s.close()

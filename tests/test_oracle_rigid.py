@@ -1,6 +1,7 @@
 """Pins of the oracle's rigid-body update (Sec. 1.3, Eqs. (15), (16)) and of
 whole-step invariants of the coupled method."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -81,7 +82,8 @@ def test_centred_circle_in_couette_has_no_lift():
     cfg = C.couette_config(nx, ny, tau=1.0)
     o = oracle.Oracle(cfg)
     o.add_particle(C.particle(shapes.circle(10.0, n_markers=32), 30.0, 20.0))
-    tr = o.step(1500)
+    o.set_threads(os.cpu_count() or 1)
+    tr = o.step(5000)
     assert np.abs(tr[:, 0, 1] - 20.0).max() < 1e-9
     assert np.abs(tr[:, 0, 0] - 30.0).max() < 1e-9
     U = cfg["u_wall"][3][0]

@@ -168,5 +168,84 @@ def adjoint_case(storage=STORE_F32, y0=15.75, theta0=math.pi / 4, aspect_ratio=2
                     2000, storage)
 
 
+# ---- the paper's own experiments at full scale (Secs. 2 and 3) ----
+
+PAPER_SPACING = 0.3  # marker spacing over the lattice spacing (Secs. 2.1, 2.2, 3.1)
+
+
+def paper_couette_config(L=100, re=20.0, u_wall=0.01, storage=STORE_F32):
+    """Sec. 3.1: a channel of 10 L x 4 L (periodic in x), bottom wall fixed,
+    top wall at u_wall, Re = u_wall H / nu = 20 with H = 4 L the wall gap,
+    started on the planar Couette profile.  With u_wall = 0.01 and L = 100
+    (so that dt u_wall / L = 1e-4): nu = 0.2, tau = 1.1."""
+    H = 4 * L
+    nu = u_wall * H / re
+    tau = 3.0 * nu + 0.5
+    uw = [[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [u_wall, 0.0]]
+    return base_config(10 * L, H + 1, tau, bc_y=ZOUHE, u_wall=uw, init=INIT_COUETTE, storage=storage)
+
+
+def paper_couette_shape(family, L=100, spacing=PAPER_SPACING):
+    """The particle families of Sec. 3 with L_ref = L: circle (diameter),
+    ellipse of aspect ratio 2 (major axis), square (edge), equilateral
+    triangle (edge) and the rectangle of aspect ratio 10 (long edge)."""
+    if family == "rectangle":
+        return shapes.rectangle(L, 10.0, spacing)
+    return shapes.make(family, L, aspect_ratio=2.0, spacing=spacing)
+
+
+def paper_couette(cases, L=100, storage=STORE_F32):
+    """One channel per (family, release height y0/H, initial x velocity over
+    u_wall) of Sec. 3: neutrally buoyant, at rest (or at the given x
+    velocity), released at x = 5 L."""
+    chans = []
+    for fam, yfrac, u0 in cases:
+        cfg = paper_couette_config(L, storage=storage)
+        H = cfg["ny"] - 1
+        uw = cfg["u_wall"][3][0]
+        sh = paper_couette_shape(fam, L)
+        chans.append((cfg, [particle(sh, 5.0 * L, yfrac * H, 0.0, 1.0, u=u0 * uw)]))
+    return Workload(f"paper Couette transport {10 * L}x{4 * L + 1}, {len(cases)} channels", chans, 0, storage)
+
+
+def paper_sedimentation_circle(N, storage=STORE_F32, spacing=PAPER_SPACING, re=0.1):
+    """Sec. 2.1 at resolution N (points per diameter): a closed box of
+    4 N x 30 N lattice spacings, tau = 1, a circle of diameter N released at
+    rest at (2 N, 28 N), density ratio 1.2, and the terminal Reynolds number
+    Re = U N / nu = 0.1 of the paper.  The printed Froude number cannot hold
+    with it in this channel (g = U^2 / (1398.3 N) gives a terminal Re near
+    6e-8), so gravity is set from the wall-corrected Stokes drag of a
+    cylinder midway between plane walls (Faxen): with k = D / W = 1/4,
+    F / (mu U) = 4 pi / (ln(1/k) - 0.9157 + 1.7244 k^2 - 1.7302 k^4), and
+    (rho_s - rho_f) A g = F.  The terminal velocity actually reached is
+    measured, not assumed.  Returns the channel and U."""
+    tau = 1.0
+    nu = (tau - 0.5) / 3.0
+    U = re * nu / N
+    k = 0.25
+    lam = 4.0 * math.pi / (math.log(1.0 / k) - 0.9157 + 1.7244 * k ** 2 - 1.7302 * k ** 4)
+    area = math.pi * N * N / 4.0
+    g = lam * nu * U / ((1.2 - 1.0) * area)
+    cfg = base_config(4 * N + 1, 30 * N + 1, tau, bc_x=ZOUHE, bc_y=ZOUHE, gravity=[0.0, -g],
+                      storage=storage)
+    sh = shapes.circle(N, spacing=spacing)
+    return (cfg, [particle(sh, 2.0 * N, 28.0 * N, 0.0, 1.2)]), U
+
+
+def paper_sedimentation_ellipse(kernel=0, L=100, storage=STORE_F64, spacing=PAPER_SPACING):
+    """Sec. 2.2: a closed box of 4 L x 30 L, tau = 1, an ellipse of major axis
+    L and aspect ratio 2 released at rest at (2 L, 24 L) with theta0 = pi/4,
+    density ratio 1.1, Re = u L / nu = 12.5, Fr = u / sqrt(L g) = 0.126,
+    interpolation kernel `kernel`."""
+    tau = 1.0
+    nu = (tau - 0.5) / 3.0
+    u = 12.5 * nu / L
+    g = u * u / (0.126 ** 2 * L)
+    cfg = base_config(4 * L + 1, 30 * L + 1, tau, bc_x=ZOUHE, bc_y=ZOUHE, gravity=[0.0, -g],
+                      storage=storage, mls_kernel=kernel)
+    sh = shapes.ellipse(L, 2.0, spacing=spacing)
+    return (cfg, [particle(sh, 2.0 * L, 24.0 * L, math.pi / 4, 1.1)]), u
+
+
 BY_NAME = dict(sedimentation=sedimentation, couette=couette, ensemble=ensemble, large=large,
                adjoint=adjoint_case)
