@@ -102,7 +102,11 @@ typedef struct lbm_channel_config {
     double gravity[2];       /* gravity on the particles, applied as
                                 (1 - rho_f/rho_s) g */
     int32_t storage;         /* LBM_STORE_* */
-    int32_t fp16_exp;        /* scale exponent K of the F16S form (0..14) */
+    int32_t fp16_exp;        /* scale exponent K of the F16S form (0..24):
+                                the largest scaled deviation s_i (f_i - w_i)
+                                must stay below the FP16 maximum 65504, so K
+                                goes down as the flow's Mach number goes up
+                                (14 suits |u| up to about 0.05) */
     double mls_rw;           /* MLS support size r_w (Sec. 1.2: 2.6) */
     double mls_alpha;        /* exponential-kernel width (Eq. (10): 0.3) */
     double probe_dn;         /* probe length along the normal (Sec. 1.3: 1.2) */

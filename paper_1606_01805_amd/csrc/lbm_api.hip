@@ -196,7 +196,7 @@ static int validate_cfg(const lbm_channel_config& c, int idx) {
     if (c.init != LBM_INIT_REST && c.init != LBM_INIT_COUETTE) return bad("bad init");
     if (c.init == LBM_INIT_COUETTE && c.bc_y != LBM_BC_ZOUHE) return bad("Couette start needs walls on y");
     if (c.storage < LBM_STORE_F64 || c.storage > LBM_STORE_F16S) return bad("bad storage");
-    if (c.fp16_exp < 0 || c.fp16_exp > 14) return bad("fp16_exp must be in 0..14");
+    if (c.fp16_exp < 0 || c.fp16_exp > 24) return bad("fp16_exp must be in 0..24");
     if (!finite_all(&c.u_wall[0][0], 8) || !finite_all(c.body_force, 2) || !finite_all(c.gravity, 2))
         return bad("non-finite wall speed, body force or gravity");
     for (int s = 0; s < 4; ++s)

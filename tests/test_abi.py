@@ -53,7 +53,7 @@ def _cfg(**kw):
     dict(nx=2), dict(ny=1), dict(tau=0.5), dict(tau=float("nan")),
     dict(bc_x=1, bc_y=1, u_wall=((0, 0), (0, 0), (0.01, 0), (0, 0))),
     dict(bc_x=1, bc_y=1, body_force=(1e-6, 0.0)),
-    dict(bc_x=3), dict(init=1), dict(storage=7), dict(fp16_exp=15), dict(mls_rw=1.0),
+    dict(bc_x=3), dict(init=1), dict(storage=7), dict(fp16_exp=25), dict(mls_rw=1.0),
     dict(mls_alpha=0.0), dict(probe_dn=-1.0), dict(mls_kernel=5), dict(spread_scale=2),
     dict(u_wall=((1.5, 0), (0, 0), (0, 0), (0, 0))), dict(gravity=(float("inf"), 0.0)),
 ])
