@@ -10,9 +10,10 @@
              each centroid at t u_wall / L = 10, 50 and 500 (the local slip
              profiles of Sec. 3.2).
   refine     Sec. 2.1: the circle settling in the closed 4 N x 30 N box at
-             N = 20, 40, 80 and 160 points per diameter, Re = 0.1, Fr = 1398.3,
-             density ratio 1.2, tau = 1; terminal velocity per N (mesh
-             refinement study).
+             N = 20, 40, 80 and 160 points per diameter, terminal Re = 0.1
+             (gravity from the wall-corrected Stokes drag, see
+             workloads.configs.paper_sedimentation_circle), density ratio
+             1.2, tau = 1; terminal velocity per N (mesh refinement study).
   kernels    Sec. 2.2: the ellipse (AR 2, L = 100) settling from (2 L, 24 L)
              with theta0 = pi/4, Re = 12.5, Fr = 0.126, density ratio 1.1, with
              each of the five interpolation kernels (Eqs. (10), (17)-(20)) as
@@ -226,7 +227,13 @@ def summarize_refine(path):
     for a, b in zip(Ns[:-2], Ns[1:-1]):
         ea, eb = vt[a]["rel_error_vs_finest"], vt[b]["rel_error_vs_finest"]
         orders[f"{a}->{b}"] = math.log(ea / eb) / math.log(b / a)
-    return dict(resolutions=vt, observed_order=orders)
+    # order from three successive resolutions, free of the finest one's own
+    # error: p = log2((v_a - v_b) / (v_b - v_c)) for N_c = 2 N_b = 4 N_a
+    rich = {}
+    for a, b, c in zip(Ns[:-2], Ns[1:-1], Ns[2:]):
+        va, vb, vc = (vt[n]["v_over_u_inf"] for n in (a, b, c))
+        rich[f"{a},{b},{c}"] = math.log(abs(va - vb) / abs(vb - vc)) / math.log(b / a)
+    return dict(resolutions=vt, observed_order_vs_finest=orders, observed_order_three_levels=rich)
 
 
 def summarize_kernels(path, y_probe=18.0):

@@ -50,18 +50,9 @@ def couette_speed(ny, tau=1.0, re=20.0):
     return re * nu / (ny - 1)
 
 
-def fp16_exp_for(u_max):
-    """Scale exponent K of the F16S storage for a flow whose speeds stay below
-    u_max: K = 14 keeps the largest scaled deviation of a flow at |u| = 0.053
-    about 18 times below the FP16 maximum; every halving of the speed allows
-    one more bit of resolution, up to K = 24."""
-    return int(min(24, 14 + max(0, math.floor(math.log2(0.053 / max(abs(u_max), 1e-12))))))
-
-
 def couette_config(nx, ny, tau=1.0, re=20.0, **kw):
     U = couette_speed(ny, tau, re)
     uw = [[0.0, 0.0], [0.0, 0.0], [-U, 0.0], [U, 0.0]]
-    kw.setdefault("fp16_exp", fp16_exp_for(U))
     return base_config(nx, ny, tau, bc_y=ZOUHE, u_wall=uw, init=INIT_COUETTE, **kw)
 
 
