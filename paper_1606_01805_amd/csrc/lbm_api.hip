@@ -232,7 +232,9 @@ extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) 
 // (256 / tile_w) * rows rows; the combined lattice / surface-stress launch
 // runs 64-wide tiles in workgroups of the particle kernel's size (9 waves).
 static int tile_height(const lbm_tuning& t) {
-    if (t.vec) return 4 * t.rows_per_thread;  // one wave per rows_per_thread rows
+    // the vector form: one wave per rows_per_thread rows (9 waves in the
+    // combined launch)
+    if (t.vec) return (t.overlap ? kIbmThreads / 64 : 4) * t.rows_per_thread;
     return t.overlap ? kIbmThreads / 64 * t.rows_per_thread : (256 / t.tile_w) * t.rows_per_thread;
 }
 
@@ -585,7 +587,7 @@ static int finalize(lbm_handle* h) {
 // launches, or one combined launch in the overlap mode.
 static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
     if (h->tune.overlap) {
-        HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
+        HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->tune.vec, h->stream));
     } else {
         HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->tune.vec, h->stream));
         HIPCHK(h, launch_traction(h->store, a, h->stream));
@@ -863,7 +865,12 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
         if (t->tile_w % 64 != 0 || (nv != 1 && nv != 2 && nv != 4 && nv != 8) || nv * (int)h->elem > 16)
             FAIL(h, LBM_EINVAL, "vec = 1 needs tile_w = 64 * nv with nv in {1, 2, 4, 8} and nv * element size <= 16 bytes");
         if (t->rows_per_thread > 2) FAIL(h, LBM_EINVAL, "vec = 1 needs rows_per_thread 1 or 2");
-        if (t->overlap) FAIL(h, LBM_EINVAL, "vec = 1 cannot be combined with overlap = 1");
+        if (t->overlap) {
+            const int es = (int)h->elem;
+            if (t->rows_per_thread != 1 || nv * es < 8 || t->persistent_wgs != 0)
+                FAIL(h, LBM_EINVAL, "vec = 1 with overlap = 1 needs rows_per_thread 1, persistent_wgs 0 and "
+                                    "chunks of 8 or 16 bytes (tile_w / 64 * element size)");
+        }
     }
     if (t->rows_per_thread != 1 && t->rows_per_thread != 2 && t->rows_per_thread != 4)
         FAIL(h, LBM_EINVAL, "rows_per_thread must be 1, 2 or 4");
@@ -871,7 +878,7 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
     if (t->use_graph != 0 && t->use_graph != 1) FAIL(h, LBM_EINVAL, "use_graph must be 0 or 1");
     if (t->xcd_remap != 0 && t->xcd_remap != 1) FAIL(h, LBM_EINVAL, "xcd_remap must be 0 or 1");
     if (t->overlap != 0 && t->overlap != 1) FAIL(h, LBM_EINVAL, "overlap must be 0 or 1");
-    if (t->overlap && (t->tile_w != 64 || t->persistent_wgs != 0))
+    if (t->overlap && !t->vec && (t->tile_w != 64 || t->persistent_wgs != 0))
         FAIL(h, LBM_EINVAL, "overlap = 1 needs tile_w = 64 and persistent_wgs = 0");
     const bool tiles = t->tile_w != h->tune.tile_w || tile_height(*t) != tile_height(h->tune);
     h->tune = *t;
@@ -923,7 +930,7 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
                 if (h->tune.overlap) {
                     // the combined launch without its particle workgroups
                     a.nwork = 0;
-                    HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->stream));
+                    HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->tune.vec, h->stream));
                 } else {
                     HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->tune.vec, h->stream));
                 }

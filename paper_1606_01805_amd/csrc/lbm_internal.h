@@ -103,9 +103,10 @@ hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s);
 // Force patches of particles of several rounds from their partial patches
 // (after launch_ibm_force).
 hipError_t launch_patch_sum(const StepArgs& a, hipStream_t s);
-// Lattice pass and surface stress in one launch (tile_w 64, tile_h 9 * npt,
-// no persistent workgroups).
-hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, hipStream_t s);
+// Lattice pass and surface stress in one launch (tile_h 9 * npt, no
+// persistent workgroups; tile_w 64, or with vec = 1 the vector form with
+// tile_w = 64 * nv and npt = 1).
+hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, int vec, hipStream_t s);
 // Plain copy of n16 16-byte elements (lbm_measure_copy).
 hipError_t launch_copy(void* dst, const void* src, long long n16, hipStream_t s);
 hipError_t launch_fields(int store, const StepArgs& a, int chan, int nx, int ny, double* f_out,

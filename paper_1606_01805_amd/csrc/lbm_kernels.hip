@@ -1025,6 +1025,26 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs 
     if (t < a.ntiles) lattice_tile<ST, 64, NPT>(a, t, (int)threadIdx.x % 64, (int)threadIdx.x / 64);
 }
 
+// The same launch with the vector form of the lattice pass: lattice tiles of
+// 64 NV x 9 nodes (one row per wave of the 9-wave workgroup).
+template <int ST, int NV, bool NT>
+__global__ __launch_bounds__(kIbmThreads) void lattice_traction_vkernel(StepArgs a, int tb) {
+    const int j = (int)blockIdx.x - tb;
+    if (j < 0) {
+        if ((int)blockIdx.x < a.nwork) {
+            const int4 wk = a.work[blockIdx.x];
+            traction_body<ST>(a, wk.x, wk.y, wk.z);
+        }
+        return;
+    }
+    int t = j;
+    if (a.xcd_remap) {
+        const int per = ((int)gridDim.x - tb) / 8;
+        t = (j % 8) * per + j / 8;
+    }
+    if (t < a.ntiles) lattice_vtile<ST, NV, 1, NT>(a, t, (int)threadIdx.x % 64, (int)threadIdx.x / 64);
+}
+
 // ---------------------------------------------------------------------------
 // Initial state, field extraction, population upload.
 // ---------------------------------------------------------------------------
@@ -1273,13 +1293,46 @@ static hipError_t lattice_traction_dispatch(const StepArgs& a, int npt, int tb, 
     return hipGetLastError();
 }
 
-hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, hipStream_t s) {
-    if (a.persistent > 0 || a.tile_w != 64 || a.tile_h != 9 * npt) return hipErrorInvalidValue;
+template <int ST, int NV>
+static hipError_t lattice_traction_vdispatch_nv(const StepArgs& a, int tb, int grid, hipStream_t s) {
+    if (a.nt_store) lattice_traction_vkernel<ST, NV, true><<<grid, kIbmThreads, 0, s>>>(a, tb);
+    else lattice_traction_vkernel<ST, NV, false><<<grid, kIbmThreads, 0, s>>>(a, tb);
+    return hipGetLastError();
+}
+
+// The vector combined launch is built for the chunk widths that fill 16 or 8
+// bytes: nv 1, 2 (FP64), 2, 4 (FP32), 4, 8 (F16S).
+template <int ST>
+static hipError_t lattice_traction_vdispatch(const StepArgs& a, int tb, int grid, hipStream_t s) {
+    const int nv = a.tile_w / 64;
+    if constexpr (ST == ST_F64) {
+        if (nv == 1) return lattice_traction_vdispatch_nv<ST, 1>(a, tb, grid, s);
+        if (nv == 2) return lattice_traction_vdispatch_nv<ST, 2>(a, tb, grid, s);
+    } else if constexpr (ST == ST_F32) {
+        if (nv == 2) return lattice_traction_vdispatch_nv<ST, 2>(a, tb, grid, s);
+        if (nv == 4) return lattice_traction_vdispatch_nv<ST, 4>(a, tb, grid, s);
+    } else {
+        if (nv == 4) return lattice_traction_vdispatch_nv<ST, 4>(a, tb, grid, s);
+        if (nv == 8) return lattice_traction_vdispatch_nv<ST, 8>(a, tb, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, int vec, hipStream_t s) {
+    if (a.persistent > 0 || a.tile_h != 9 * npt) return hipErrorInvalidValue;
+    if (vec ? npt != 1 : a.tile_w != 64) return hipErrorInvalidValue;
     const long long tb = a.nwork > 0 ? ((long long)a.nwork + 7) / 8 * 8 : 0;
     const long long tl = a.xcd_remap ? ((long long)a.ntiles + 7) / 8 * 8 : a.ntiles;
     const long long grid = tb + tl;
     if (grid <= 0) return hipSuccess;
     if (grid > INT_MAX) return hipErrorInvalidValue;
+    if (vec) {
+        switch (store) {
+            case ST_F64: return lattice_traction_vdispatch<ST_F64>(a, (int)tb, (int)grid, s);
+            case ST_F32: return lattice_traction_vdispatch<ST_F32>(a, (int)tb, (int)grid, s);
+            default: return lattice_traction_vdispatch<ST_F16S>(a, (int)tb, (int)grid, s);
+        }
+    }
     switch (store) {
         case ST_F64: return lattice_traction_dispatch<ST_F64>(a, npt, (int)tb, (int)grid, s);
         case ST_F32: return lattice_traction_dispatch<ST_F32>(a, npt, (int)tb, (int)grid, s);

@@ -206,8 +206,11 @@ def test_couette_256x64_gradients_match_oracle_fd(storage, tol):
     |D(h) - D(h/2)| = 3/4 |D(h) - R| (R the Richardson value): over 2000
     steps the rounding noise of J divided by the small h the anchors allow
     reaches ~1e-5 of the smaller derivatives.  tol = 1e-5 for FP64
-    populations; 5e-3 for FP32 populations, where the forward map itself is
-    the rounded one (measured worst 2.2e-3, d omega / d y0)."""
+    populations; 5e-3 for FP32 populations (measured worst 3.9e-3 for
+    d omega / d U and 2.2e-3 for d omega / d y0).  The FP32 gap comes from
+    the FP32 forward states the tape holds, around which the step map is
+    linearised: holding the adjoint populations in FP64 instead of FP32
+    leaves both errors unchanged (measured)."""
     gold, out, gy, gw = _couette_256x64(storage)
     print("final", out[0, :6], "oracle y", gold["y"], "omega", gold["omega"])
     bad = []

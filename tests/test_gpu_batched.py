@@ -161,16 +161,20 @@ def test_full_large_domain_sampled_steps(storage, key, tol_pos, tol_f):
     assert e_pos < tol_pos and e_F < tol_f, (e_pos, e_F)
 
 
-@pytest.mark.parametrize("storage,tw", [(C.STORE_F32, 256), (C.STORE_F16S, 512), (C.STORE_F64, 128)])
-def test_vector_form_coupled_bitwise(storage, tw):
+@pytest.mark.parametrize("storage,tw,overlap", [(C.STORE_F32, 256, 0), (C.STORE_F16S, 512, 0), (C.STORE_F64, 128, 0),
+                                                (C.STORE_F32, 256, 1), (C.STORE_F16S, 256, 1), (C.STORE_F64, 128, 1)])
+def test_vector_form_coupled_bitwise(storage, tw, overlap):
     """Batched uneven channels with particles: the vector form of the lattice
     pass gives bitwise the trajectories and populations of the per-node
-    form (the IB force added per node, several particles per tile)."""
+    form (the IB force added per node, several particles per tile), also in
+    the combined launch with the surface stress (overlap = 1, tiles of
+    tile_w x 9)."""
     chans = _small_ensemble(storage)
     s0, g0 = run_gpu(chans, 120)
     p0 = [s0.populations(k) for k in range(len(chans))]
     s0.close()
-    s1, g1 = run_gpu(chans, 120, tuning=dict(vec=1, tile_w=tw, rows_per_thread=2, nt_store=1))
+    rows = 1 if overlap else 2
+    s1, g1 = run_gpu(chans, 120, tuning=dict(vec=1, tile_w=tw, rows_per_thread=rows, nt_store=1, overlap=overlap))
     p1 = [s1.populations(k) for k in range(len(chans))]
     s1.close()
     assert np.array_equal(g0, g1)
