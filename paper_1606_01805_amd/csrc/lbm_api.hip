@@ -552,7 +552,9 @@ static int finalize(lbm_handle* h) {
     long long pcells = 0;
     for (int k = 0; k < np; ++k) {
         const int nr = (pd[k].nm + kRound - 1) / kRound;
-        for (int r = 0; r < nr; ++r) work.push_back(make_int4(k, r, pd[k].chan, 0));
+        for (int r = 0; r < nr; ++r)
+            work.push_back(work_entry(k, r, std::min(kRound, pd[k].nm - r * kRound), pd[k].chan,
+                                      pd[k].mbeg + r * kRound));
         pd[k].part_off = pcells;
         if (nr > 1) {
             pcells += (long long)nr * pd[k].patch_cap;

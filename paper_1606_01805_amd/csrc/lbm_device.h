@@ -533,6 +533,53 @@ __device__ __forceinline__ void patch_force_tab(const ChanDev& c, const PatchRef
     }
 }
 
+// patch_force_tab for the NV consecutive nodes [xb, xb + NV) of row y at
+// once (nodes at or past the channel's last column excluded): per node the
+// same terms in the same order, with each round's values for all NV nodes
+// requested together rather than node by node.
+template <int NV>
+__device__ __forceinline__ void patch_force_row(const ChanDev& c, const PatchRef* tab, int n, int xb, int y,
+                                               double (&fx)[NV], double (&fy)[NV]) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) fx[j] = fy[j] = 0.0;
+    for (int e = 0; e < n; ++e) {
+        const PatchRef R = tab[e];
+        int dy = y - R.by0;
+        if (c.bcy == 0 && dy < 0) dy += c.ny;
+        if (dy < 0 || dy >= R.bh) continue;
+        const double2* row = R.base + (long long)dy * R.bw;
+        bool in[NV];
+        int cx[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            int dx = xb + j - R.bx0;
+            if (c.bcx == 0 && dx < 0) dx += c.nx;
+            in[j] = xb + j < c.nx && dx >= 0 && dx < R.bw;
+            cx[j] = in[j] ? dx : 0;
+        }
+        double2 v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = in[j] ? row[cx[j]] : make_double2(0.0, 0.0);
+        for (int r = 1; r < R.nr; ++r) {
+            const double2* pr = row + (long long)r * R.cap;
+            double2 u[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) u[j] = in[j] ? pr[cx[j]] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                v[j].x += u[j].x;
+                v[j].y += u[j].y;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (in[j]) {
+                fx[j] += v[j].x;
+                fy[j] += v[j].y;
+            }
+    }
+}
+
 // Inserts v into the ascending register list L[0, n) unless present.
 template <int N>
 __device__ __forceinline__ void list_insert(int (&L)[N], int& n, int v) {
@@ -625,10 +672,8 @@ struct Marker {
     int i0, j0;
 };
 
-__device__ __forceinline__ Marker marker_at(const StepArgs& a, int idx, double X0, double X1,
-                                            double cs, double sn) {
+__device__ __forceinline__ Marker marker_from(double2 x, double X0, double X1, double cs, double sn) {
     Marker m;
-    const double2 x = a.xi[idx];
     m.rx = cs * x.x - sn * x.y;
     m.ry = sn * x.x + cs * x.y;
     m.xl = X0 + m.rx;
@@ -636,6 +681,11 @@ __device__ __forceinline__ Marker marker_at(const StepArgs& a, int idx, double X
     m.i0 = (int)floor(m.xl + 0.5);
     m.j0 = (int)floor(m.yl + 0.5);
     return m;
+}
+
+__device__ __forceinline__ Marker marker_at(const StepArgs& a, int idx, double X0, double X1,
+                                            double cs, double sn) {
+    return marker_from(a.xi[idx], X0, X1, cs, sn);
 }
 
 // Stencil node k of the 3x3 support around anchor (i0, j0): distance

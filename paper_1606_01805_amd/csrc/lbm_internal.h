@@ -55,6 +55,15 @@ struct PartDev {
     long long part_off;      // first cell of the per-round partial patches (several rounds)
 };
 
+// A particle-kernel work entry carries what the first loads of a round
+// need (its markers' place in the marker arrays and their count), so that
+// the marker loads leave with the particle record's, not after it.
+__host__ __device__ inline int4 work_entry(int particle, int round, int count, int chan, int first) {
+    return make_int4(particle, round | (count << 16), chan, first);
+}
+__host__ __device__ inline int work_round(int4 w) { return w.y & 0xffff; }
+__host__ __device__ inline int work_count(int4 w) { return w.y >> 16; }
+
 struct StepArgs {
     const void* fin;         // post-collision populations of step n-1
     void* fout;              // post-collision populations of step n
@@ -79,8 +88,10 @@ struct StepArgs {
     int parity;              // which half of tlist this step fills / reads
     int tile_w, tile_h;      // tile extent in nodes
     PartDev* snap;           // optional: copy of each particle after the force stage
-    const int4* work;        // [nwork] particle-kernel workgroups: (particle, round of
-                             // kRound markers, channel, 0), particle-major
+    const int4* work;        // [nwork] particle-kernel workgroups, particle-major:
+                             // (particle, round of kRound markers | markers of the
+                             // round << 16, channel, first marker of the round in the
+                             // marker arrays); see work_entry
     int nwork;
     int* pcount;             // [nparts] finished surface-stress workgroups; 0 between launches
     double2* partial;        // per-round partial force patches of particles of several rounds

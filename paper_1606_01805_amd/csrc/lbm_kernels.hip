@@ -28,6 +28,7 @@
 // FP32.  The immersed-boundary and rigid-body stages are FP64 in every form.
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "lbm_device.h"
 
@@ -101,7 +102,7 @@ __device__ __forceinline__ bool finish_last(int* counter, int n) {
 // it and adds the group's terms in ascending marker order onto the value the
 // earlier groups left (the first group starts from zero), so each node sums
 // the round's terms in ascending marker order, with no float atomics.
-constexpr int kMaskCells = 4096;
+constexpr int kMaskCells = 3072;
 
 __device__ __forceinline__ void spread_group(const ChanDev& c, const unsigned long long* gmask,
                                             const double2* s_con, const int2* s_anc, double2* target,
@@ -146,8 +147,15 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// Two of the particle kernels' 9-wave workgroups share a CU only at six or
+// more waves per SIMD (a workgroup places three of its waves on one SIMD;
+// measured: at five waves per SIMD one workgroup runs per CU), and only
+// while each takes less than 60 KB of LDS (no third one fits beside them
+// once a workgroup takes a few KB), hence the register cap here and the
+// mask size above.
 template <int ST>
-__global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
+__global__ __launch_bounds__(kIbmThreads) __attribute__((amdgpu_waves_per_eu(6)))
+void ibm_force_kernel(StepArgs a) {
     __shared__ unsigned long long gmask[kMaskCells];  // anchor masks of the group being spread
     __shared__ double s_w[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double2 s_con[kIbmThreads];            // c_l phi_k F_l of the round
@@ -159,12 +167,16 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
     if ((int)blockIdx.x >= a.nwork) return;
     const int4 wk = a.work[blockIdx.x];
-    const int pid = wk.x;
+    const int pid = wk.x, rnd = work_round(wk), nact = work_count(wk);
     PartDev* P = a.parts + pid;
     const ChanDev c = load_chan(a.chan + wk.z);  // issued beside the particle's loads
-    const int nm = P->nm, mb = P->mbeg;
-    const int nr = (nm + kRound - 1) / kRound, r0 = wk.y * kRound;
-    const bool lead = wk.y == 0;  // the round-0 workgroup owns the particle's bookkeeping
+    // the pair's marker offset too: the work entry locates it
+    const int lo = tid / 9, k = tid % 9;
+    const bool act = lo < nact;
+    const double2 xoff = act ? a.xi[wk.w + lo] : make_double2(0.0, 0.0);
+    const int nm = P->nm;
+    const int nr = (nm + kRound - 1) / kRound;
+    const bool lead = rnd == 0;  // the round-0 workgroup owns the particle's bookkeeping
     const double X0 = P->X[0], X1 = P->X[1], th = P->th;
     const double V0 = P->V[0], V1 = P->V[1], Om = P->Om;
     const double cs = P->cth, sn = P->sth;  // the rotation R(theta)
@@ -198,7 +210,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     const int ncell = bw * bh;
     double2* patch = a.patch + P->patch_off;
     // nr partial patches of patch_cap cells (nr > 1)
-    double2* target = nr == 1 ? patch : a.partial + P->part_off + (long long)wk.y * P->patch_cap;
+    double2* target = nr == 1 ? patch : a.partial + P->part_off + (long long)rnd * P->patch_cap;
     for (int q = tid; q < kMaskCells; q += blockDim.x) gmask[q] = 0ull;
     if (lead && tid == 0) {
         P->bx0 = wrapc(bx0u, c.nx, c.bcx == 0);
@@ -207,13 +219,9 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         P->bh = bh;
         if (a.snap) a.snap[pid] = *P;
     }
-    const int lo = tid / 9, k = tid % 9;
-    const int l = r0 + lo;
-    const bool act = l < nm;
-    const int nact = nm - r0 < kRound ? nm - r0 : kRound;  // markers of this round
     // (1) one weight and the force-free velocity u* = j*/rho of one node
     if (act) {
-        const Marker m = marker_at(a, mb + l, X0, X1, cs, sn);
+        const Marker m = marker_from(xoff, X0, X1, cs, sn);
         double dx, dy;
         int ni, nj;
         double w = 0.0, ux = 0.0, uy = 0.0;
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
             s_anc[lo] = make_int2(m.i0, m.j0);
             s_mk[lo][0] = m.xl;
             s_mk[lo][1] = m.yl;
-            s_mk[lo][2] = c.spread_unit ? 1.0 : a.ds[mb + l];
+            s_mk[lo][2] = c.spread_unit ? 1.0 : a.ds[wk.w + lo];
             // the rigid-body velocity at the marker
             s_ml[lo][3] = V0 - Om * m.ry;
             s_ml[lo][4] = V1 + Om * m.rx;
@@ -241,9 +249,9 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
     __syncthreads();
     if (tid < kRound) {
         // (2) per marker, all in the first wave (thread lo leads marker
-        // r0 + lo): the MLS row, U = sum phi u* (k ascending) and
+        // lo of the round): the MLS row, U = sum phi u* (k ascending) and
         // F = U_b - U (dt = 1)
-        if (r0 + tid < nm) {
+        if (tid < nact) {
             const int lo = tid;
             const int2 an = s_anc[lo];
             const double xl = s_mk[lo][0], yl = s_mk[lo][1];
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(kIbmThreads) void ibm_force_kernel(StepArgs a) {
         }
     } else if (tid < 2 * kRound) {
         // meanwhile the second wave forms the anchor box of the whole round
-        // (lane j: marker r0 + j); when it fits the masks, they are set here
+        // (lane j: marker j of the round); when it fits the masks, they are set here
         // and the round spreads as one group
         const int j = tid - kRound;
         const bool in = j < nact;
@@ -383,17 +391,15 @@ __global__ __launch_bounds__(256) void patch_sum_kernel(StepArgs a) {
 // ---------------------------------------------------------------------------
 // FP64 form, reference expression order.  f holds the pulled populations;
 // out receives the post-collision populations of node (x, y).
-__device__ __forceinline__ void collide_f64(const StepArgs& a, const ChanDev& c,
-                                            const ChanDev* cm, int x,
-                                            int y, double f[9], const PatchRef* tab, int nlist,
-                                            const char* __restrict__ fin, double out[9]) {
+// (flbx, flby): the IB force at the node.
+__device__ __forceinline__ void collide_f64_force(const StepArgs& a, const ChanDev& c,
+                                                  const ChanDev* cm, int x, int y, double f[9],
+                                                  double flbx, double flby,
+                                                  const char* __restrict__ fin, double out[9]) {
     walls_f64(c, *cm, x, y, f);
     corners_f64(fin, c, x, y, f);
     double rho, jx, jy;
     moments_f64(f, c, rho, jx, jy);
-    double flbx = 0.0, flby = 0.0;
-    if (nlist >= kTileList) patch_force(a, c, x, y, flbx, flby);
-    else if (nlist > 0) patch_force_tab(c, tab, nlist, x, y, flbx, flby);
     const double gx = c.g[0], gy = c.g[1];
     const double ux = (jx + 0.5 * flbx) / rho;
     const double uy = (jy + 0.5 * flby) / rho;
@@ -417,6 +423,17 @@ __device__ __forceinline__ void collide_f64(const StepArgs& a, const ChanDev& c,
     }
 }
 
+// The same with the IB force read from the tile's patch table.
+__device__ __forceinline__ void collide_f64(const StepArgs& a, const ChanDev& c,
+                                            const ChanDev* cm, int x,
+                                            int y, double f[9], const PatchRef* tab, int nlist,
+                                            const char* __restrict__ fin, double out[9]) {
+    double flbx = 0.0, flby = 0.0;
+    if (nlist >= kTileList) patch_force(a, c, x, y, flbx, flby);
+    else if (nlist > 0) patch_force_tab(c, tab, nlist, x, y, flbx, flby);
+    collide_f64_force(a, c, cm, x, y, f, flbx, flby, fin, out);
+}
+
 __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanDev& c,
                                                   const ChanDev* cm, int x,
                                                   int y, double f[9], const PatchRef* tab, int nlist,
@@ -428,24 +445,17 @@ __device__ __forceinline__ void collide_store_f64(const StepArgs& a, const ChanD
 }
 
 // Reduced forms: deviations in FP32.  d holds the pulled deviations; out
-// receives the post-collision deviations of node (x, y).
+// receives the post-collision deviations of node (x, y); (flbx, flby): the
+// IB force at the node, rounded to FP32.
 template <int ST>
-__device__ __forceinline__ void collide_dev(const StepArgs& a, const ChanDev& c,
-                                            const ChanDev* cm, int x,
-                                            int y, float d[9], const PatchRef* tab, int nlist,
-                                            const char* __restrict__ fin, float out[9]) {
+__device__ __forceinline__ void collide_dev_force(const StepArgs& a, const ChanDev& c,
+                                                  const ChanDev* cm, int x, int y, float d[9],
+                                                  float flbx, float flby,
+                                                  const char* __restrict__ fin, float out[9]) {
     walls_dev(c, *cm, x, y, d);
     corners_dev<ST>(fin, c, x, y, d);
     const float drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const float rho = 1.0f + drho;
-    float flbx = 0.0f, flby = 0.0f;
-    if (nlist > 0) {
-        double fx, fy;
-        if (nlist >= kTileList) patch_force(a, c, x, y, fx, fy);
-        else patch_force_tab(c, tab, nlist, x, y, fx, fy);
-        flbx = (float)fx;
-        flby = (float)fy;
-    }
     const float gx = c.f_g[0], gy = c.f_g[1];
     const float jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]) + 0.5f * (gx + flbx);
     const float jy = ((d[2] - d[4]) + (d[5] + d[6])) - (d[7] + d[8]) + 0.5f * (gy + flby);
@@ -482,6 +492,23 @@ __device__ __forceinline__ void collide_dev(const StepArgs& a, const ChanDev& c,
         a.flags[0] = 1;
         atomicMin(&a.flags[1], (int)(*a.dstep - 1));
     }
+}
+
+// The same with the IB force read from the tile's patch table.
+template <int ST>
+__device__ __forceinline__ void collide_dev(const StepArgs& a, const ChanDev& c,
+                                            const ChanDev* cm, int x,
+                                            int y, float d[9], const PatchRef* tab, int nlist,
+                                            const char* __restrict__ fin, float out[9]) {
+    float flbx = 0.0f, flby = 0.0f;
+    if (nlist > 0) {
+        double fx, fy;
+        if (nlist >= kTileList) patch_force(a, c, x, y, fx, fy);
+        else patch_force_tab(c, tab, nlist, x, y, fx, fy);
+        flbx = (float)fx;
+        flby = (float)fy;
+    }
+    collide_dev_force<ST>(a, c, cm, x, y, d, flbx, flby, fin, out);
 }
 
 template <int ST>
@@ -682,6 +709,34 @@ __device__ __forceinline__ void lattice_vtile(const StepArgs& a, int t, int lane
             if (j < nlist && (int)threadIdx.x == j) s_tab[j] = patch_ref(a, a.parts[list[j]]);
         __syncthreads();
     }
+    // With up to four nodes per lane, the IB force of the lane's nodes is
+    // loaded first, every patch value requested at once (node by node, each
+    // node's patch loads would wait for the pulls and then for each other);
+    // with eight, that costs more registers than it saves.
+    constexpr bool kEarly = NV <= 4;
+    using FT = typename std::conditional<ST == ST_F64, double, float>::type;
+    FT gfx[NPT][NV], gfy[NPT][NV];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int y = ty0 + wv * NPT + r;
+        double fx[NV], fy[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) fx[j] = fy[j] = 0.0;
+        if (kEarly && nlist > 0 && xin && y < c.ny) {
+            if (nlist >= kTileList) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    if (xbl + j < c.nx) patch_force(a, c, xbl + j, y, fx[j], fy[j]);
+            } else {
+                patch_force_row<NV>(c, s_tab, nlist, xbl, y, fx, fy);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            gfx[r][j] = (FT)fx[j];
+            gfy[r][j] = (FT)fy[j];
+        }
+    }
     T raw[NPT][9][NV];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
@@ -702,7 +757,10 @@ __device__ __forceinline__ void lattice_vtile(const StepArgs& a, int t, int lane
                 double f[9], o[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) f[i] = raw[r][i][j];
-                if (x < c.nx) collide_f64(a, c, cm, x, y, f, s_tab, nlist, fin, o);
+                if (x < c.nx) {
+                    if constexpr (kEarly) collide_f64_force(a, c, cm, x, y, f, gfx[r][j], gfy[r][j], fin, o);
+                    else collide_f64(a, c, cm, x, y, f, s_tab, nlist, fin, o);
+                }
                 else
 #pragma unroll
                     for (int i = 0; i < 9; ++i) o[i] = 0.0;
@@ -712,7 +770,10 @@ __device__ __forceinline__ void lattice_vtile(const StepArgs& a, int t, int lane
                 float d[9], o[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) d[i] = load_dev<ST>(&raw[r][i][j], 0, i, c);
-                if (x < c.nx) collide_dev<ST>(a, c, cm, x, y, d, s_tab, nlist, fin, o);
+                if (x < c.nx) {
+                    if constexpr (kEarly) collide_dev_force<ST>(a, c, cm, x, y, d, gfx[r][j], gfy[r][j], fin, o);
+                    else collide_dev<ST>(a, c, cm, x, y, d, s_tab, nlist, fin, o);
+                }
                 else
 #pragma unroll
                     for (int i = 0; i < 9; ++i) o[i] = 0.0f;
@@ -725,8 +786,15 @@ __device__ __forceinline__ void lattice_vtile(const StepArgs& a, int t, int lane
     }
 }
 
+// Waves per SIMD the one-row FP32 vector pass is held to (its occupancy
+// before the IB force of its nodes was loaded ahead of the pulls); the
+// other shapes are left to the compiler.
+template <int ST, int NPT>
+constexpr int kVecWaves = NPT == 1 && ST == ST_F32 ? 5 : 1;
+
 template <int ST, int NV, int NPT, bool NT>
-__global__ __launch_bounds__(256) void lattice_vkernel(StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kVecWaves<ST, NPT>)))
+void lattice_vkernel(StepArgs a) {
     const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
     const int stride = a.persistent ? (int)gridDim.x : a.ntiles;
     int t0 = blockIdx.x;
@@ -760,15 +828,24 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
 // marker's traction.
 // ---------------------------------------------------------------------------
 template <int ST>
-__device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd, int ch) {
+__device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) {
     __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double s_t[3][kRound];
     __shared__ double s_pg[kRound][7];  // marker: r_x, r_y, n_x, n_y, probe x, probe y, S
     __shared__ int2 s_pa[kRound];       // probe stencil anchor
     __shared__ double sums[3];
     const int tid = threadIdx.x;
+    const int b = wk.x, rnd = work_round(wk), nact = work_count(wk);
     PartDev* P = a.parts + b;
-    const ChanDev c = load_chan(a.chan + ch);  // issued beside the particle's loads
+    const ChanDev c = load_chan(a.chan + wk.z);  // issued beside the particle's loads
+    // and the pair's marker offset and normal, located by the work entry
+    const int lo = tid / 9, k = tid % 9;
+    const bool mk = lo < nact;
+    double2 xoff = make_double2(0.0, 0.0), noff = xoff;
+    if (mk) {
+        xoff = a.xi[wk.w + lo];
+        noff = a.nrm[wk.w + lo];
+    }
     const int nm = P->nm, mb = P->mbeg;
     const double X0 = P->X[0], X1 = P->X[1], th = P->th, Om = P->Om;
     const double acc0 = P->acc[0], acc1 = P->acc[1], alp = P->alp;
@@ -781,10 +858,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     const int nr = (nm + kRound - 1) / kRound;
     const bool multi = nr > 1 && !skip;
     const double cs = skip ? 1.0 : P->cth, sn = skip ? 0.0 : P->sth;
-    const int lo = tid / 9, k = tid % 9;
-    const int r0 = rnd * kRound;
-    const int l = r0 + lo;
-    const bool act = !skip && l < nm;
+    const bool act = !skip && mk;
     // (0) the probe stencil node of the pair and its stored populations,
     // loaded before the neighbour list is known (only the patch forces need
     // it), so the two latencies overlap
@@ -793,7 +867,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     bool node = false;
     typename Sto<ST>::T raw[9];
     if (act) {
-        const double2 x = a.xi[mb + l], nb = a.nrm[mb + l];
+        const double2 x = xoff, nb = noff;
         rx = cs * x.x - sn * x.y;
         ry = sn * x.x + cs * x.y;
         nxl = cs * nb.x - sn * nb.y;
@@ -858,14 +932,14 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
                 s_pg[lo][3] = nyl;
                 s_pg[lo][4] = xp;
                 s_pg[lo][5] = yp;
-                s_pg[lo][6] = a.ds[mb + l];
+                s_pg[lo][6] = a.ds[wk.w + lo];
                 s_pa[lo] = make_int2(i0, j0);
             }
         }
         __syncthreads();
-        if (tid < kRound && r0 + tid < nm) {
-            // marker r0 + lm, led from the first wave
-            const int lm = tid, l = r0 + lm, lo = lm;
+        if (tid < nact) {
+            // marker lm of the round, led from the first wave
+            const int lm = tid, lo = lm;
             const double rx = s_pg[lo][0], ry = s_pg[lo][1];
             const double nxl = s_pg[lo][2], nyl = s_pg[lo][3];
             const double xp = s_pg[lo][4], yp = s_pg[lo][5];
@@ -901,7 +975,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
             const double S = s_pg[lo][6];
             const double t0 = tx * S, t1 = ty * S, t2 = (rx * ty - ry * tx) * S;
             if (multi) {
-                double* o = a.mscr + (long long)(mb + l) * 4;
+                double* o = a.mscr + (long long)(wk.w + lm) * 4;
                 pub_store(o, t0);
                 pub_store(o + 1, t1);
                 pub_store(o + 2, t2);
@@ -991,11 +1065,15 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, int b, int rnd,
     }
 }
 
-template <int ST>
-__global__ __launch_bounds__(kIbmThreads) void traction_kernel(StepArgs a) {
+// PAIR: the register cap that lets two workgroups share a CU, for launches
+// of more rounds than CUs; it spills a few registers, which costs a single
+// round about a microsecond, so smaller launches take the plain kernel.
+template <int ST, bool PAIR>
+__global__ __launch_bounds__(kIbmThreads) __attribute__((amdgpu_waves_per_eu(PAIR ? 6 : 1)))
+void traction_kernel(StepArgs a) {
     if ((int)blockIdx.x < a.nwork) {
         const int4 wk = a.work[blockIdx.x];
-        traction_body<ST>(a, wk.x, wk.y, wk.z);
+        traction_body<ST>(a, wk);
     }
 }
 
@@ -1013,7 +1091,7 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs 
     if (j < 0) {
         if ((int)blockIdx.x < a.nwork) {
             const int4 wk = a.work[blockIdx.x];
-            traction_body<ST>(a, wk.x, wk.y, wk.z);
+            traction_body<ST>(a, wk);
         }
         return;
     }
@@ -1033,7 +1111,7 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_vkernel(StepArgs
     if (j < 0) {
         if ((int)blockIdx.x < a.nwork) {
             const int4 wk = a.work[blockIdx.x];
-            traction_body<ST>(a, wk.x, wk.y, wk.z);
+            traction_body<ST>(a, wk);
         }
         return;
     }
@@ -1276,9 +1354,26 @@ hipError_t launch_patch_sum(const StepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Compute units of the current device (queried once per device).
+static int cu_count() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 hipError_t launch_traction(int store, const StepArgs& a, hipStream_t s) {
     if (a.nwork <= 0) return hipSuccess;
-#define L_(ST) traction_kernel<ST><<<a.nwork, kIbmThreads, 0, s>>>(a)
+    const bool pair = a.nwork > cu_count();
+#define L_(ST)                                                                          \
+    if (pair) traction_kernel<ST, true><<<a.nwork, kIbmThreads, 0, s>>>(a);            \
+    else traction_kernel<ST, false><<<a.nwork, kIbmThreads, 0, s>>>(a)
     LBM_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();
