@@ -12,8 +12,8 @@ over the kept steps and particles:
 Bars: FP32 on the 400 x 100 Couette channel over 50 000 steps, FP16S on the
 4096 x 1024 domain with 64 particles over 10 000 steps; the other pairings
 are reported with looser bars.  The FP32 bar planned for the Couette channel
-was 1e-4; the measured errors over 50 000 steps are 1.15e-4 (position),
-1.53e-4 (angle) and 1.02e-4 (angular velocity): the ellipse tumbles, so the
+was 1e-4; the measured errors over 50 000 steps are 1.12e-4 (position),
+1.36e-4 (angle) and 0.93e-4 (angular velocity): the ellipse tumbles, so the
 ~6e-8 relative rounding of every FP32 intermediate (the velocity, the
 equilibrium terms) becomes a phase error of its rotation that grows faster
 than the step count (4.5e-6 rad at 6 700 steps).  The bar is 2.5e-4.
