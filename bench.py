@@ -167,8 +167,11 @@ def measured_traffic(key):
 def roofline(us_lattice, nodes, storage, traffic_key=None, tuning=None, ms_step=None):
     b = nodes * BYTES_PER_LUP[storage]
     ach = b / (us_lattice * 1e-6) / 1e9
-    name = ("lattice_traction_kernel (lattice workgroups only)" if tuning and tuning.get("overlap")
-            else "lattice_kernel")
+    vec = bool(tuning and tuning.get("vec"))
+    if tuning and tuning.get("overlap"):
+        name = ("lattice_traction_vkernel" if vec else "lattice_traction_kernel") + " (lattice workgroups only)"
+    else:
+        name = "lattice_vkernel" if vec else "lattice_kernel"
     out = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
            "traffic": measured_traffic(traffic_key) if traffic_key else None,
