@@ -43,12 +43,12 @@ REPEATS = 5
 # Launch shapes picked by the autotuner (paper_1606_01805_amd/tune.py) per
 # workload and storage form.
 WORKLOAD_TUNING = {"couette": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1),
-                   "ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1)}
-VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1),
-                  "large": dict(tile_w=128, rows_per_thread=2, xcd_remap=1),
-                  "large16": dict(tile_w=256, rows_per_thread=1, xcd_remap=1, vec=1),
-                  "huge": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1),
-                  "huge16": dict(tile_w=512, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1)}
+                   "ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1, overlap=1)}
+VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1, overlap=1),
+                  "large": dict(tile_w=256, rows_per_thread=1, xcd_remap=1, vec=1, overlap=1),
+                  "large16": dict(tile_w=256, rows_per_thread=1, xcd_remap=1, vec=1, overlap=1),
+                  "huge": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1, overlap=1),
+                  "huge16": dict(tile_w=512, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1, overlap=1)}
 
 
 def parse():

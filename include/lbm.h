@@ -147,11 +147,12 @@ typedef struct lbm_tuning {
                                 the step's input populations and force
                                 patches): the first workgroups take the
                                 particles' rounds of 64 markers, the rest
-                                take lattice tiles of
-                                64 x 9*rows_per_thread nodes (tile_w x 9 with
-                                vec = 1).  Needs persistent_wgs = 0, and
-                                tile_w = 64 unless vec = 1 (else
-                                LBM_EINVAL); results are bitwise those of 0 */
+                                take lattice tiles: 64 x 9*rows_per_thread
+                                nodes in 576-thread workgroups (vec = 0), or
+                                the vec = 1 tiles in 256-thread workgroups.
+                                Needs persistent_wgs = 0, and tile_w = 64
+                                unless vec = 1 (else LBM_EINVAL); results are
+                                bitwise those of 0 */
     int32_t vec;             /* 1: vector form of the lattice pass: each lane
                                 takes nv = tile_w / 64 consecutive nodes of a
                                 row and moves each population plane of them
@@ -159,10 +160,8 @@ typedef struct lbm_tuning {
                                 (at most 16 bytes: nv <= 2 in FP64, 4 in
                                 FP32, 8 in F16S; tile_w 512 is allowed for
                                 F16S); tiles of tile_w x 4 * rows_per_thread
-                                nodes, rows_per_thread 1 or 2.  With
-                                overlap = 1 (the combined launch): tiles of
-                                tile_w x 9, rows_per_thread 1, chunks of 8 or
-                                16 bytes.  Results are bitwise those of
+                                nodes, rows_per_thread 1 or 2 (1 with
+                                overlap = 1).  Results are bitwise those of
                                 vec = 0 */
     int32_t nt_store;        /* 1 (needs vec = 1): the lattice pass stores
                                 nontemporally, bypassing the caches; faster

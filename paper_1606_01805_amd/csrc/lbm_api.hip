@@ -230,11 +230,12 @@ extern "C" size_t lbm_workspace_bytes(const lbm_channel_config* cfg, int32_t n) 
 
 // Tile height of the lattice pass: 256-thread workgroups cover
 // (256 / tile_w) * rows rows; the combined lattice / surface-stress launch
-// runs 64-wide tiles in workgroups of the particle kernel's size (9 waves).
+// of the per-node form runs 64-wide tiles in workgroups of the particle
+// kernel's size (9 waves).
 static int tile_height(const lbm_tuning& t) {
-    // the vector form: one wave per rows_per_thread rows (9 waves in the
-    // combined launch)
-    if (t.vec) return (t.overlap ? kIbmThreads / 64 : 4) * t.rows_per_thread;
+    // the vector form, alone or combined: one wave per rows_per_thread rows
+    // of a 256-thread workgroup
+    if (t.vec) return 4 * t.rows_per_thread;
     return t.overlap ? kIbmThreads / 64 * t.rows_per_thread : (256 / t.tile_w) * t.rows_per_thread;
 }
 
@@ -867,12 +868,8 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
         if (t->tile_w % 64 != 0 || (nv != 1 && nv != 2 && nv != 4 && nv != 8) || nv * (int)h->elem > 16)
             FAIL(h, LBM_EINVAL, "vec = 1 needs tile_w = 64 * nv with nv in {1, 2, 4, 8} and nv * element size <= 16 bytes");
         if (t->rows_per_thread > 2) FAIL(h, LBM_EINVAL, "vec = 1 needs rows_per_thread 1 or 2");
-        if (t->overlap) {
-            const int es = (int)h->elem;
-            if (t->rows_per_thread != 1 || nv * es < 8 || t->persistent_wgs != 0)
-                FAIL(h, LBM_EINVAL, "vec = 1 with overlap = 1 needs rows_per_thread 1, persistent_wgs 0 and "
-                                    "chunks of 8 or 16 bytes (tile_w / 64 * element size)");
-        }
+        if (t->overlap && (t->rows_per_thread != 1 || t->persistent_wgs != 0))
+            FAIL(h, LBM_EINVAL, "vec = 1 with overlap = 1 needs rows_per_thread 1 and persistent_wgs 0");
     }
     if (t->rows_per_thread != 1 && t->rows_per_thread != 2 && t->rows_per_thread != 4)
         FAIL(h, LBM_EINVAL, "rows_per_thread must be 1, 2 or 4");

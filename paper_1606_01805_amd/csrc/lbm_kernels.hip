@@ -835,20 +835,86 @@ __global__ __launch_bounds__(256) void lattice_kernel(StepArgs a) {
 // of each marker builds the probe's MLS value and gradient weights and the
 // marker's traction.
 // ---------------------------------------------------------------------------
+// Probe geometry of one (marker, probe-stencil node) pair: the marker's
+// offset and normal rotated by theta, its probe point x_l + dn n_l, the
+// probe stencil anchor and the pair's node (false: dropped beyond a wall).
+struct ProbePair {
+    double rx, ry, nxl, nyl, xp, yp, dx, dy;
+    int i0, j0, ni, nj;
+    bool node;
+};
+
+__device__ __forceinline__ ProbePair probe_pair(const ChanDev& c, double2 x, double2 nb, int k, double X0,
+                                                double X1, double cs, double sn, double dn) {
+    ProbePair g;
+    g.rx = cs * x.x - sn * x.y;
+    g.ry = sn * x.x + cs * x.y;
+    g.nxl = cs * nb.x - sn * nb.y;
+    g.nyl = sn * nb.x + cs * nb.y;
+    g.xp = X0 + g.rx + dn * g.nxl;
+    g.yp = X1 + g.ry + dn * g.nyl;
+    g.i0 = (int)floor(g.xp + 0.5);
+    g.j0 = (int)floor(g.yp + 0.5);
+    g.node = stencil_node(c, g.i0, g.j0, k, g.xp, g.yp, g.dx, g.dy, g.ni, g.nj);
+    return g;
+}
+
+// The pair's weight and force-corrected fields at its node (rho = 1, u = 0
+// and weight 0 at a dropped node), into the round's LDS rows; the k = 0
+// pair of a marker also stores the marker's geometry.
 template <int ST>
+__device__ __forceinline__ void probe_fields(const StepArgs& a, const ChanDev& c, const ProbePair& g,
+                                             const typename Sto<ST>::T (&raw)[9], const int* s_nb,
+                                             int nnb, int p, int lo, int k, double ds, double* s_w,
+                                             double* s_r, double* s_ux, double* s_uy,
+                                             double (*s_pg)[7], int2* s_pa) {
+    double w = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
+    if (g.node) {
+        w = stencil_weight(c, g.dx, g.dy);
+        double f[9], jx, jy, fx, fy;
+        pull_finish_f64<ST>(a.fin, c, g.ni, g.nj, raw, f);
+        moments_f64(f, c, rho, jx, jy);
+        if (nnb <= kMaxNeighbours) patch_force_list(a, c, s_nb, nnb, g.ni, g.nj, fx, fy);
+        else patch_force(a, c, g.ni, g.nj, fx, fy);
+        ux = (jx + 0.5 * fx) / rho;
+        uy = (jy + 0.5 * fy) / rho;
+    }
+    s_w[p] = w;
+    s_r[p] = rho;
+    s_ux[p] = ux;
+    s_uy[p] = uy;
+    if (k == 0) {
+        s_pg[lo][0] = g.rx;
+        s_pg[lo][1] = g.ry;
+        s_pg[lo][2] = g.nxl;
+        s_pg[lo][3] = g.nyl;
+        s_pg[lo][4] = g.xp;
+        s_pg[lo][5] = g.yp;
+        s_pg[lo][6] = ds;
+        s_pa[lo] = make_int2(g.i0, g.j0);
+    }
+}
+
+// TPB threads per round: 576 (one pair per thread, whose loads leave before
+// the neighbour list is built), or 256 (the combined launch with the
+// vector lattice pass: each thread takes pairs tid, tid + 256, tid + 512 in
+// turn).  The arithmetic of each pair and marker, and every sum, is the
+// same in both.
+template <int ST, int TPB = kIbmThreads>
 __device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) {
     __shared__ double s_w[kIbmThreads], s_r[kIbmThreads], s_ux[kIbmThreads], s_uy[kIbmThreads];
     __shared__ double s_t[3][kRound];
     __shared__ double s_pg[kRound][7];  // marker: r_x, r_y, n_x, n_y, probe x, probe y, S
     __shared__ int2 s_pa[kRound];       // probe stencil anchor
     __shared__ double sums[3];
+    constexpr bool kOnePair = TPB == kIbmThreads;
     const int tid = threadIdx.x;
     const int b = wk.x, rnd = work_round(wk), nact = work_count(wk);
     PartDev* P = a.parts + b;
     const ChanDev c = load_chan(a.chan + wk.z);  // issued beside the particle's loads
     // and the pair's marker offset and normal, located by the work entry
     const int lo = tid / 9, k = tid % 9;
-    const bool mk = lo < nact;
+    const bool mk = kOnePair && lo < nact;
     double2 xoff = make_double2(0.0, 0.0), noff = xoff;
     if (mk) {
         xoff = a.xi[wk.w + lo];
@@ -867,25 +933,14 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) 
     const bool multi = nr > 1 && !skip;
     const double cs = skip ? 1.0 : P->cth, sn = skip ? 0.0 : P->sth;
     const bool act = !skip && mk;
-    // (0) the probe stencil node of the pair and its stored populations,
-    // loaded before the neighbour list is known (only the patch forces need
-    // it), so the two latencies overlap
-    double rx = 0.0, ry = 0.0, nxl = 0.0, nyl = 0.0, xp = 0.0, yp = 0.0, dx = 0.0, dy = 0.0;
-    int i0 = 0, j0 = 0, ni = 0, nj = 0;
-    bool node = false;
+    // (0) with one pair per thread, the probe stencil node of the pair and
+    // its stored populations, loaded before the neighbour list is known
+    // (only the patch forces need it), so the two latencies overlap
+    ProbePair g0 = {};
     typename Sto<ST>::T raw[9];
     if (act) {
-        const double2 x = xoff, nb = noff;
-        rx = cs * x.x - sn * x.y;
-        ry = sn * x.x + cs * x.y;
-        nxl = cs * nb.x - sn * nb.y;
-        nyl = sn * nb.x + cs * nb.y;
-        xp = X0 + rx + dn * nxl;
-        yp = X1 + ry + dn * nyl;
-        i0 = (int)floor(xp + 0.5);
-        j0 = (int)floor(yp + 0.5);
-        node = stencil_node(c, i0, j0, k, xp, yp, dx, dy, ni, nj);
-        if (node) pull_load<ST>(a.fin, c, ni, nj, raw);
+        g0 = probe_pair(c, xoff, noff, k, X0, X1, cs, sn, dn);
+        if (g0.node) pull_load<ST>(a.fin, c, g0.ni, g0.nj, raw);
     }
     // Particles of the channel whose force patches can reach this particle's
     // probe stencils (its own box grown by the probe reach), ascending.
@@ -917,31 +972,19 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) 
     const int nnb = s_nnb;
 
     if (!skip) {
-        if (act) {
-            double w = 0.0, rho = 1.0, ux = 0.0, uy = 0.0;
-            if (node) {
-                w = stencil_weight(c, dx, dy);
-                double f[9], jx, jy, fx, fy;
-                pull_finish_f64<ST>(a.fin, c, ni, nj, raw, f);
-                moments_f64(f, c, rho, jx, jy);
-                if (nnb <= kMaxNeighbours) patch_force_list(a, c, s_nb, nnb, ni, nj, fx, fy);
-                else patch_force(a, c, ni, nj, fx, fy);
-                ux = (jx + 0.5 * fx) / rho;
-                uy = (jy + 0.5 * fy) / rho;
-            }
-            s_w[tid] = w;
-            s_r[tid] = rho;
-            s_ux[tid] = ux;
-            s_uy[tid] = uy;
-            if (k == 0) {
-                s_pg[lo][0] = rx;
-                s_pg[lo][1] = ry;
-                s_pg[lo][2] = nxl;
-                s_pg[lo][3] = nyl;
-                s_pg[lo][4] = xp;
-                s_pg[lo][5] = yp;
-                s_pg[lo][6] = a.ds[wk.w + lo];
-                s_pa[lo] = make_int2(i0, j0);
+        if constexpr (kOnePair) {
+            if (act)
+                probe_fields<ST>(a, c, g0, raw, s_nb, nnb, tid, lo, k, k == 0 ? a.ds[wk.w + lo] : 0.0, s_w,
+                                 s_r, s_ux, s_uy, s_pg, s_pa);
+        } else {
+            for (int p = tid; p < kIbmThreads; p += TPB) {
+                const int lp = p / 9, kp = p % 9;
+                if (lp >= nact) continue;
+                const ProbePair g = probe_pair(c, a.xi[wk.w + lp], a.nrm[wk.w + lp], kp, X0, X1, cs, sn, dn);
+                typename Sto<ST>::T rp[9];
+                if (g.node) pull_load<ST>(a.fin, c, g.ni, g.nj, rp);
+                probe_fields<ST>(a, c, g, rp, s_nb, nnb, p, lp, kp, kp == 0 ? a.ds[wk.w + lp] : 0.0, s_w,
+                                 s_r, s_ux, s_uy, s_pg, s_pa);
             }
         }
         __syncthreads();
@@ -1001,7 +1044,7 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) 
     // 192 markers at a time, every thread loading one term.
     double fsum = 0.0;
     if (multi) {
-        constexpr int kStage = kIbmThreads / 3;
+        constexpr int kStage = TPB / 3;
         for (int base = 0; base < nm; base += kStage) {
             const int l = base + tid / 3;
             s_w[tid] = l < nm ? pub_load(a.mscr + (long long)(mb + l) * 4 + tid % 3) : 0.0;
@@ -1111,15 +1154,19 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs 
     if (t < a.ntiles) lattice_tile<ST, 64, NPT>(a, t, (int)threadIdx.x % 64, (int)threadIdx.x / 64);
 }
 
-// The same launch with the vector form of the lattice pass: lattice tiles of
-// 64 NV x 9 nodes (one row per wave of the 9-wave workgroup).
+// The same launch with the vector form of the lattice pass, in 256-thread
+// workgroups: the lattice tiles are those of lattice_vkernel (64 NV x 4
+// nodes), and a particle round runs its 576 (marker, node) pairs on 256
+// threads.  With at most 96 VGPRs and the surface stress's 24 KB of LDS,
+// five such workgroups share a CU, as in lattice_vkernel.
 template <int ST, int NV, bool NT>
-__global__ __launch_bounds__(kIbmThreads) void lattice_traction_vkernel(StepArgs a, int tb) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F32 ? 5 : ST == ST_F16S ? 4 : 1)))
+void lattice_traction_vkernel(StepArgs a, int tb) {
     const int j = (int)blockIdx.x - tb;
     if (j < 0) {
         if ((int)blockIdx.x < a.nwork) {
             const int4 wk = a.work[blockIdx.x];
-            traction_body<ST>(a, wk);
+            traction_body<ST, 256>(a, wk);
         }
         return;
     }
@@ -1398,8 +1445,8 @@ static hipError_t lattice_traction_dispatch(const StepArgs& a, int npt, int tb, 
 
 template <int ST, int NV>
 static hipError_t lattice_traction_vdispatch_nv(const StepArgs& a, int tb, int grid, hipStream_t s) {
-    if (a.nt_store) lattice_traction_vkernel<ST, NV, true><<<grid, kIbmThreads, 0, s>>>(a, tb);
-    else lattice_traction_vkernel<ST, NV, false><<<grid, kIbmThreads, 0, s>>>(a, tb);
+    if (a.nt_store) lattice_traction_vkernel<ST, NV, true><<<grid, 256, 0, s>>>(a, tb);
+    else lattice_traction_vkernel<ST, NV, false><<<grid, 256, 0, s>>>(a, tb);
     return hipGetLastError();
 }
 
@@ -1407,23 +1454,23 @@ static hipError_t lattice_traction_vdispatch_nv(const StepArgs& a, int tb, int g
 // bytes: nv 1, 2 (FP64), 2, 4 (FP32), 4, 8 (F16S).
 template <int ST>
 static hipError_t lattice_traction_vdispatch(const StepArgs& a, int tb, int grid, hipStream_t s) {
-    const int nv = a.tile_w / 64;
-    if constexpr (ST == ST_F64) {
-        if (nv == 1) return lattice_traction_vdispatch_nv<ST, 1>(a, tb, grid, s);
-        if (nv == 2) return lattice_traction_vdispatch_nv<ST, 2>(a, tb, grid, s);
-    } else if constexpr (ST == ST_F32) {
-        if (nv == 2) return lattice_traction_vdispatch_nv<ST, 2>(a, tb, grid, s);
-        if (nv == 4) return lattice_traction_vdispatch_nv<ST, 4>(a, tb, grid, s);
-    } else {
-        if (nv == 4) return lattice_traction_vdispatch_nv<ST, 4>(a, tb, grid, s);
-        if (nv == 8) return lattice_traction_vdispatch_nv<ST, 8>(a, tb, grid, s);
+    constexpr int kMaxNv = 16 / (int)sizeof(typename Sto<ST>::T);
+    switch (a.tile_w / 64) {
+        case 1: return lattice_traction_vdispatch_nv<ST, 1>(a, tb, grid, s);
+        case 2: return lattice_traction_vdispatch_nv<ST, 2>(a, tb, grid, s);
+        case 4:
+            if constexpr (kMaxNv >= 4) return lattice_traction_vdispatch_nv<ST, 4>(a, tb, grid, s);
+            return hipErrorInvalidValue;
+        case 8:
+            if constexpr (kMaxNv >= 8) return lattice_traction_vdispatch_nv<ST, 8>(a, tb, grid, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_lattice_traction(int store, const StepArgs& a, int npt, int vec, hipStream_t s) {
-    if (a.persistent > 0 || a.tile_h != 9 * npt) return hipErrorInvalidValue;
-    if (vec ? npt != 1 : a.tile_w != 64) return hipErrorInvalidValue;
+    if (a.persistent > 0 || (vec ? npt != 1 || a.tile_h != 4 : a.tile_w != 64 || a.tile_h != 9 * npt))
+        return hipErrorInvalidValue;
     const long long tb = a.nwork > 0 ? ((long long)a.nwork + 7) / 8 * 8 : 0;
     const long long tl = a.xcd_remap ? ((long long)a.ntiles + 7) / 8 * 8 : a.ntiles;
     const long long grid = tb + tl;

@@ -39,6 +39,9 @@ def candidates(n_nodes):
                 for nt in (0, 1):
                     out.append(dict(tile_w=tw, rows_per_thread=rows, persistent_wgs=0, xcd_remap=remap,
                                     overlap=0, vec=1, nt_store=nt))
+                    if rows == 1:  # the vector form combined with the surface stress
+                        out.append(dict(tile_w=tw, rows_per_thread=1, persistent_wgs=0, xcd_remap=remap,
+                                        overlap=1, vec=1, nt_store=nt))
     return [dict(dict(vec=0, nt_store=0), **c) for c in out]
 
 

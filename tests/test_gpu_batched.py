@@ -85,10 +85,18 @@ def test_batched_multi_round_particles(storage):
     chans = _multi_round_channels(storage)
     s, g = run_gpu(chans, 120)
     s.close()
-    # the surface stress beside the lattice pass in one launch: bitwise the same
+    # the surface stress beside the lattice pass in one launch: bitwise the
+    # same, in the per-node form (576-thread workgroups) and in the vector
+    # form (256-thread workgroups: each thread takes three probe pairs in
+    # turn, and the last round's workgroup sums the published terms in
+    # stages of 85 markers)
     s2, g2 = run_gpu(chans, 120, tuning=dict(overlap=1, tile_w=64, rows_per_thread=2))
     s2.close()
     assert np.array_equal(g, g2)
+    tw = 128 if storage == C.STORE_F64 else 256
+    s3, g3 = run_gpu(chans, 120, tuning=dict(overlap=1, vec=1, tile_w=tw, rows_per_thread=1))
+    s3.close()
+    assert np.array_equal(g, g3)
     pid = 0
     for ci, (cfg, parts) in enumerate(chans):
         s1, g1 = run_gpu([(cfg, parts)], 120)
@@ -162,13 +170,14 @@ def test_full_large_domain_sampled_steps(storage, key, tol_pos, tol_f):
 
 
 @pytest.mark.parametrize("storage,tw,overlap", [(C.STORE_F32, 256, 0), (C.STORE_F16S, 512, 0), (C.STORE_F64, 128, 0),
-                                                (C.STORE_F32, 256, 1), (C.STORE_F16S, 256, 1), (C.STORE_F64, 128, 1)])
+                                                (C.STORE_F32, 256, 1), (C.STORE_F16S, 256, 1), (C.STORE_F64, 128, 1),
+                                                (C.STORE_F32, 64, 1), (C.STORE_F16S, 512, 1)])
 def test_vector_form_coupled_bitwise(storage, tw, overlap):
     """Batched uneven channels with particles: the vector form of the lattice
     pass gives bitwise the trajectories and populations of the per-node
     form (the IB force added per node, several particles per tile), also in
-    the combined launch with the surface stress (overlap = 1, tiles of
-    tile_w x 9)."""
+    the combined launch with the surface stress (overlap = 1: the same tiles
+    in 256-thread workgroups, a round's 576 probe pairs on 256 threads)."""
     chans = _small_ensemble(storage)
     s0, g0 = run_gpu(chans, 120)
     p0 = [s0.populations(k) for k in range(len(chans))]

@@ -197,7 +197,7 @@ def test_combined_launch_fp64_parity_with_overlapping_patches():
 def test_wide_rounds_spread_in_groups_fp64():
     """A 120-unit square rotated by 45 degrees with markers 3 apart (160
     markers, 3 rounds): the stencil anchors of each round of 64 markers span
-    more than the 4096-cell mask box, so every round spreads in several
+    more than the 3072-cell mask box, so every round spreads in several
     marker groups.  FP64 against the oracle, and FP32 bitwise equal whether
     the channel runs alone or beside another."""
     cfg = C.couette_config(400, 240, storage=C.STORE_F64)
