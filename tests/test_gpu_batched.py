@@ -147,6 +147,28 @@ def test_full_ensemble_sampled_channels():
         assert np.abs(g[:, ch, 9] - ch).max() == 0
 
 
+def test_full_ensemble_equals_its_halves():
+    """The full ensemble at full size in the benchmark's launch shape: its
+    566 rounds of 64 markers take more than the 512 workgroups that two per
+    CU hold on a 256-CU part, so its particle kernels run in two batches,
+    while each half of it (under 512 rounds) runs in one.  The particle
+    records of every channel are bitwise those of the half it belongs to."""
+    from bench import VARIANT_TUNING
+
+    wl = C.ensemble(storage=C.STORE_F32)
+    rounds = sum((len(p["xi"]) + 63) // 64 for _, ps in wl.channels for p in ps)
+    assert rounds > 512, rounds
+    steps = 30
+    s, g = run_gpu(wl.channels, steps, tuning=VARIANT_TUNING["ensemble"])
+    s.close()
+    for lo, hi in ((0, 128), (128, 256)):
+        half = wl.channels[lo:hi]
+        assert sum((len(p["xi"]) + 63) // 64 for _, ps in half for p in ps) <= 512
+        s, h = run_gpu(half, steps, tuning=VARIANT_TUNING["ensemble"])
+        s.close()
+        assert np.array_equal(g[:, lo:hi, :9], h[:, :, :9]), (lo, hi)
+
+
 # FP16S keeps about 11 bits of each scaled deviation: velocities carry a
 # relative error of order 1e-5 (|u| <= 0.05), i.e. about 1e-6 lattice units
 # of displacement over 3 steps, against 1e-8 for FP32.
