@@ -43,6 +43,7 @@ REPEATS = 5
 # Launch shapes picked by the autotuner (paper_1606_01805_amd/tune.py) per
 # workload and storage form.
 WORKLOAD_TUNING = {"couette": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1),
+                   "sedimentation": dict(tile_w=64, rows_per_thread=1, xcd_remap=0, overlap=1),
                    "ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1, overlap=1)}
 VARIANT_TUNING = {"ensemble": dict(tile_w=256, rows_per_thread=1, xcd_remap=0, vec=1, nt_store=1, overlap=1),
                   "large": dict(tile_w=256, rows_per_thread=1, xcd_remap=1, vec=1, overlap=1),
@@ -245,18 +246,19 @@ def run_variant(name, storage, steps, warm, plain=False, tuning=None, traffic_ke
     return out
 
 
-def adjoint_leg(storage=1, steps=2000, seg=100):
+def adjoint_leg(storage=1, steps=2000, seg=100, tuning=None):
     """Cost of one reverse-mode gradient on the 256x64 Couette case: the
     checkpointed forward (graph replay, a checkpoint every `seg` steps) and
     the adjoint sweep (every segment recomputed into the tape and reversed),
-    per step, and their ratio."""
+    per step, and their ratio, with the library's default launch shape or
+    `tuning` for both."""
     import torch
 
     from paper_1606_01805_amd import Solver
     from workloads import configs as C
 
     wl = C.adjoint_case(storage=storage)
-    s = Solver(wl.channels)
+    s = Solver(wl.channels, tuning=tuning)
     nseg = steps // seg
     s.checkpoint_save(nseg + 1)
     s.step(200, record=False)  # warm-up (graphs built)
@@ -281,8 +283,10 @@ def adjoint_leg(storage=1, steps=2000, seg=100):
         s.adjoint_segment(k, seg)
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
+    s_tuning = s.tuning()
     s.close()
     return {"workload": wl.name, "storage": STORE_NAME[storage], "steps": steps, "segment": seg,
+            "tuning": s_tuning,
             "forward_us_per_step": t_plain / steps * 1e6,
             "forward_checkpointed_us_per_step": t_fwd / steps * 1e6,
             "adjoint_us_per_step": t_adj / steps * 1e6,
@@ -420,13 +424,17 @@ def main():
         out["variants"] = [
             run_variant("ensemble", 1, 30, 6, plain=True),
             run_variant("couette", 1, 4000, 400, tuning=WORKLOAD_TUNING["couette"], traffic_key="couette_f32"),
-            run_variant("sedimentation", 0, 2000, 200),
+            run_variant("sedimentation", 0, 2000, 200, tuning=WORKLOAD_TUNING["sedimentation"]),
             run_variant("large", 1, 500, 50, tuning=VARIANT_TUNING["large"], traffic_key="large_f32"),
             run_variant("large", 2, 500, 50, tuning=VARIANT_TUNING["large16"], traffic_key="large_f16s"),
             run_variant("huge", 1, 100, 10, tuning=VARIANT_TUNING["huge"], traffic_key="huge_f32"),
             run_variant("huge", 2, 100, 10, tuning=VARIANT_TUNING["huge16"], traffic_key="huge_f16s"),
         ]
         out["adjoint"] = adjoint_leg()
+        # the same with the forward step in its fastest launch shape (the
+        # surface stress beside the lattice pass), which the recomputation
+        # uses too: the adjoint kernels do not change, the forward step does
+        out["adjoint_fast_forward"] = adjoint_leg(tuning=WORKLOAD_TUNING["couette"])
         out["trajectory_error"] = trajectory_errors()
     if args.workload == "adjoint":
         out["adjoint"] = adjoint_leg(storage=storage)
