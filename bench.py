@@ -268,21 +268,32 @@ def adjoint_leg(storage=1, steps=2000, seg=100, tuning=None):
     s.step(steps, record=False)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    s.checkpoint_restore(nseg + 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(nseg):
-        s.checkpoint_save(k)
-        s.step(seg, record=False)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
     seed = [[0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0]]
-    t0 = time.perf_counter()
-    s.adjoint_begin(seed, seg)
-    for k in reversed(range(nseg)):
-        s.adjoint_segment(k, seg)
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
+
+    def forward_and_adjoint(sweep):
+        # the checkpointed forward run, then the gradient: every segment
+        # recomputed into a tape and reversed, either one after the other or
+        # with the next segment's recomputation beside the current reversal
+        s.checkpoint_restore(nseg + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nseg):
+            s.checkpoint_save(k)
+            s.step(seg, record=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.adjoint_begin(seed, seg)
+        if sweep:
+            s.adjoint_sweep(list(reversed(range(nseg))), seg)
+        else:
+            for k in reversed(range(nseg)):
+                s.adjoint_segment(k, seg)
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1
+
+    forward_and_adjoint(True)  # allocates the second tape
+    t_fwd, t_adj = forward_and_adjoint(True)
+    _, t_seq = forward_and_adjoint(False)
     s_tuning = s.tuning()
     s.close()
     return {"workload": wl.name, "storage": STORE_NAME[storage], "steps": steps, "segment": seg,
@@ -291,7 +302,11 @@ def adjoint_leg(storage=1, steps=2000, seg=100, tuning=None):
             "forward_checkpointed_us_per_step": t_fwd / steps * 1e6,
             "adjoint_us_per_step": t_adj / steps * 1e6,
             "adjoint_over_forward": t_adj / t_plain,
-            "note": "adjoint time includes recomputing each segment from its checkpoint"}
+            "adjoint_segments_one_by_one_us_per_step": t_seq / steps * 1e6,
+            "adjoint_segments_one_by_one_over_forward": t_seq / t_plain,
+            "note": "adjoint time includes recomputing each segment from its checkpoint (lbm_adjoint_sweep: "
+                    "the next segment's recomputation beside the current reversal; also timed with "
+                    "lbm_adjoint_segment one segment after the other)"}
 
 
 def trajectory_errors():

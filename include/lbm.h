@@ -303,6 +303,21 @@ int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_segment);
  * adjoint is then abandoned). */
 int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n_steps);
 
+/* Reverse n_segments segments of n_steps each, from the last one backwards:
+ * slots[j] (host array of n_segments) holds the checkpoint n_steps before
+ * that of slots[j - 1], and slots[0] the one n_steps before the adjoint
+ * position.  Gives bitwise the results of lbm_adjoint_segment called on each
+ * slot in turn, and leaves the forward state at the checkpoint of the last
+ * slot.  The recomputation of segment j + 1 runs on a second stream of the
+ * library beside the reversal of segment j (the checkpointing schedule is
+ * unchanged: each segment is recomputed once), which takes a second tape of
+ * max_segment steps, allocated at the first call and freed with the first
+ * tape; where it does not fit, the segments run one after the other.
+ * Errors: those of lbm_adjoint_segment; LBM_EUNSTABLE / LBM_ECAPACITY of any
+ * segment are reported after the last one (the adjoint is then
+ * abandoned). */
+int lbm_adjoint_sweep(lbm_handle* h, const int32_t* slots, int32_t n_segments, int32_t n_steps);
+
 /* Gradients at the current adjoint position (host outputs, each may be NULL):
  *   part_out   [n_particles][LBM_AGRAD] (layout above), particles in the
  *              order added; at position 0 entries [17, 25) are the

@@ -72,6 +72,7 @@ SIGNATURES = {
     "lbm_time_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_adjoint_begin": (ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int32]),
     "lbm_adjoint_segment": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_adjoint_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "lbm_adjoint_gradients": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
     "lbm_adjoint_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _dp]),
     "lbm_measure_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,

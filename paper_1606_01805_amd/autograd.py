@@ -95,8 +95,7 @@ class LBMIBMFunction(torch.autograd.Function):
         for j, p in enumerate(order):
             seed[j, :9] = gn[p]
         s.adjoint_begin(seed, spec.segment)
-        for k in reversed(range(spec.steps // spec.segment)):
-            s.adjoint_segment(k, spec.segment)
+        s.adjoint_sweep(list(reversed(range(spec.steps // spec.segment))), spec.segment)
         part, mk, wall = s.adjoint_gradients()
         g_pose = np.zeros((npart, 6))
         g_area = np.zeros(npart)

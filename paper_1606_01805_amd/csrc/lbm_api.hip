@@ -126,6 +126,14 @@ struct lbm_handle {
     std::vector<void*> tape_f;     // post-collision populations of each taped step
     PartDev* tape_p = nullptr;     // [adj_seg + 1][nparts] particle snapshots
     double2* tape_patch = nullptr; // [adj_seg][cells] force patches
+    // lbm_adjoint_sweep: a second tape, filled on a second stream while the
+    // first is reversed; events: [0], [1] tape k recomputed, [2], [3] tape k
+    // reversed
+    std::vector<void*> tape2_f;
+    PartDev* tape2_p = nullptr;
+    double2* tape2_patch = nullptr;
+    hipStream_t stream2 = nullptr;
+    hipEvent_t tape_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     void* lam[2] = {nullptr, nullptr};
     size_t lam_bytes = 0;
     int lcur = 0;
@@ -588,12 +596,12 @@ static int finalize(lbm_handle* h) {
 
 // Lattice pass and surface stress of one step, after its force stage: two
 // launches, or one combined launch in the overlap mode.
-static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
+static int enqueue_rest(lbm_handle* h, const StepArgs& a, hipStream_t s) {
     if (h->tune.overlap) {
-        HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->tune.vec, h->stream));
+        HIPCHK(h, launch_lattice_traction(h->store, a, h->tune.rows_per_thread, h->tune.vec, s));
     } else {
-        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->tune.vec, h->stream));
-        HIPCHK(h, launch_traction(h->store, a, h->stream));
+        HIPCHK(h, launch_lattice(h->store, a, h->tune.tile_w, h->tune.rows_per_thread, h->tune.vec, s));
+        HIPCHK(h, launch_traction(h->store, a, s));
     }
     return LBM_OK;
 }
@@ -601,7 +609,7 @@ static int enqueue_rest(lbm_handle* h, const StepArgs& a) {
 static int enqueue_step(lbm_handle* h, int cur) {
     StepArgs a = make_args(h, cur);
     HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-    return enqueue_rest(h, a);
+    return enqueue_rest(h, a, h->stream);
 }
 
 static int run_steps(lbm_handle* h, long long n) {
@@ -954,7 +962,18 @@ extern "C" int lbm_time_kernels(lbm_handle* h, int32_t reps, double out_us[3]) {
 // ---------------------------------------------------------------------------
 // Adjoint.
 // ---------------------------------------------------------------------------
+static void free_tape2(lbm_handle* h) {
+    for (void* p : h->tape2_f)
+        if (p) (void)hipFree(p);
+    h->tape2_f.clear();
+    if (h->tape2_p) (void)hipFree(h->tape2_p);
+    if (h->tape2_patch) (void)hipFree(h->tape2_patch);
+    h->tape2_p = nullptr;
+    h->tape2_patch = nullptr;
+}
+
 static void free_adjoint(lbm_handle* h) {
+    free_tape2(h);
     for (void* p : h->tape_f)
         if (p) (void)hipFree(p);
     h->tape_f.clear();
@@ -1087,52 +1106,85 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
     return LBM_OK;
 }
 
-extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
-    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
-    if (h->adj_pos < 0) FAIL(h, LBM_ESTATE, "no adjoint in progress (call lbm_adjoint_begin)");
-    if (slot < 0 || slot >= kCheckpoints) FAIL(h, LBM_EINVAL, "slot must be in 0..%d", kCheckpoints - 1);
-    if (n < 1 || n > h->adj_seg) FAIL(h, LBM_EINVAL, "segment length must be in 1..%d", h->adj_seg);
-    const Checkpoint& ck = h->ck[slot];
-    if (!ck.f || ck.nparts != h->nparts) FAIL(h, LBM_ESTATE, "slot %d holds no compatible checkpoint", slot);
-    if (ck.steps + n != h->adj_pos)
-        FAIL(h, LBM_ESTATE, "checkpoint at step %lld plus %d steps does not reach the adjoint position %lld",
-             ck.steps, n, h->adj_pos);
-    int r;
-    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
-    if ((r = lbm_checkpoint_restore(h, slot)) != LBM_OK) return r;
+// One tape: the recomputed states of a segment of up to adj_seg steps.
+struct TapeRef {
+    const std::vector<void*>* f;  // [n] post-collision populations
+    PartDev* p;                   // [n + 1][nparts] particle snapshots
+    double2* patch;               // [n][cells] summed force patches
+};
+
+// Recomputes the n steps that start at checkpoint ck into tape T, on stream
+// s, with no host wait: the particle state and step counter start from the
+// checkpoint, and the first step reads the checkpoint's populations in
+// place.  Writes the handle's particle state, step counter, tile lists,
+// partial patches and surface-stress scratch, none of which the reverse
+// kernels read.
+static int tape_segment(lbm_handle* h, const Checkpoint& ck, int n, const TapeRef& T, hipStream_t s) {
     const int np = h->nparts;
-    // recompute the segment into the tape
+    const size_t cells = (size_t)std::max<long long>(h->cells, 1);
+    if (np) HIPCHK(h, hipMemcpyAsync(h->dparts, ck.p, sizeof(PartDev) * np, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->dstep, ck.step, sizeof(long long), hipMemcpyDeviceToDevice, s));
+    int r;
     for (int t = 0; t < n; ++t) {
-        StepArgs a = make_args(h, h->cur, (h->cur + t) & 1);
-        a.fin = t == 0 ? h->buf[h->cur] : h->tape_f[t - 1];
-        a.fout = h->tape_f[t];
-        a.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
-        a.snap = h->tape_p + (size_t)t * np;  // particle snapshot after the force stage
+        StepArgs a = make_args(h, ck.cur, (ck.cur + t) & 1);
+        a.fin = t == 0 ? ck.f : (*T.f)[t - 1];
+        a.fout = (*T.f)[t];
+        a.patch = T.patch + (size_t)t * cells;
+        a.snap = T.p + (size_t)t * np;  // particle snapshot after the force stage
         // the tape keeps the summed patches, which the adjoint kernels read
         a.sum_partials = 0;
-        HIPCHK(h, launch_ibm_force(h->store, a, h->stream));
-        HIPCHK(h, launch_patch_sum(a, h->stream));
-        if ((r = enqueue_rest(h, a)) != LBM_OK) return r;
+        HIPCHK(h, launch_ibm_force(h->store, a, s));
+        HIPCHK(h, launch_patch_sum(a, s));
+        if ((r = enqueue_rest(h, a, s)) != LBM_OK) return r;
     }
-    if (np)
-        HIPCHK(h, hipMemcpyAsync(h->tape_p + (size_t)n * np, h->dparts, sizeof(PartDev) * np,
-                                 hipMemcpyDeviceToDevice, h->stream));
-    if ((r = check_flags(h)) != LBM_OK) return r;
-    // reverse sweep
+    if (np) HIPCHK(h, hipMemcpyAsync(T.p + (size_t)n * np, h->dparts, sizeof(PartDev) * np, hipMemcpyDeviceToDevice, s));
+    return LBM_OK;
+}
+
+// Reverses the n taped steps of the segment that starts at checkpoint ck,
+// on stream s.
+static int reverse_segment(lbm_handle* h, const Checkpoint& ck, int n, const TapeRef& T, hipStream_t s) {
+    const int np = h->nparts;
+    const size_t cells = (size_t)std::max<long long>(h->cells, 1);
     for (int t = n - 1; t >= 0; --t) {
         AdjArgs a = adj_args(h);
-        a.s.fin = t == 0 ? h->buf[h->cur] : h->tape_f[t - 1];
-        a.s.parts = h->tape_p + (size_t)t * np;
-        a.s.patch = h->tape_patch + (size_t)t * std::max<long long>(h->cells, 1);
-        a.pnext = h->tape_p + (size_t)(t + 1) * np;
+        a.s.fin = t == 0 ? ck.f : (*T.f)[t - 1];
+        a.s.parts = T.p + (size_t)t * np;
+        a.s.patch = T.patch + (size_t)t * cells;
+        a.pnext = T.p + (size_t)(t + 1) * np;
         a.first = h->adj_first ? 1 : 0;
-        HIPCHK(h, launch_adj_traction(h->store, a, h->stream));
-        HIPCHK(h, launch_adj_ibm(h->store, a, h->stream));
-        HIPCHK(h, launch_adj_lattice(h->store, a, h->stream));
+        HIPCHK(h, launch_adj_traction(h->store, a, s));
+        HIPCHK(h, launch_adj_ibm(h->store, a, s));
+        HIPCHK(h, launch_adj_lattice(h->store, a, s));
         h->lcur = 1 - h->lcur;
         h->apar = 1 - h->apar;
         h->adj_first = false;
     }
+    return LBM_OK;
+}
+
+static int check_segment(lbm_handle* h, int32_t slot, int32_t n, long long end) {
+    if (slot < 0 || slot >= kCheckpoints) FAIL(h, LBM_EINVAL, "slot must be in 0..%d", kCheckpoints - 1);
+    if (n < 1 || n > h->adj_seg) FAIL(h, LBM_EINVAL, "segment length must be in 1..%d", h->adj_seg);
+    const Checkpoint& ck = h->ck[slot];
+    if (!ck.f || ck.nparts != h->nparts) FAIL(h, LBM_ESTATE, "slot %d holds no compatible checkpoint", slot);
+    if (ck.steps + n != end)
+        FAIL(h, LBM_ESTATE, "checkpoint at step %lld plus %d steps does not reach step %lld", ck.steps, n, end);
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (h->adj_pos < 0) FAIL(h, LBM_ESTATE, "no adjoint in progress (call lbm_adjoint_begin)");
+    int r;
+    if ((r = check_segment(h, slot, n, h->adj_pos)) != LBM_OK) return r;
+    const Checkpoint& ck = h->ck[slot];
+    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
+    if ((r = lbm_checkpoint_restore(h, slot)) != LBM_OK) return r;
+    const TapeRef T{&h->tape_f, h->tape_p, h->tape_patch};
+    if ((r = tape_segment(h, ck, n, T, h->stream)) != LBM_OK) return r;
+    if ((r = check_flags(h)) != LBM_OK) return r;
+    if ((r = reverse_segment(h, ck, n, T, h->stream)) != LBM_OK) return r;
     const int rf = check_flags(h);
     // leave the forward state at the segment's checkpoint
     if ((r = lbm_checkpoint_restore(h, slot)) != LBM_OK) return r;
@@ -1141,6 +1193,73 @@ extern "C" int lbm_adjoint_segment(lbm_handle* h, int32_t slot, int32_t n) {
         return rf;
     }
     h->adj_pos -= n;
+    return LBM_OK;
+}
+
+extern "C" int lbm_adjoint_sweep(lbm_handle* h, const int32_t* slots, int32_t nseg, int32_t n) {
+    if (!h) FAIL(h, LBM_EINVAL, "handle is NULL");
+    if (h->adj_pos < 0) FAIL(h, LBM_ESTATE, "no adjoint in progress (call lbm_adjoint_begin)");
+    if (!slots || nseg < 1) FAIL(h, LBM_EINVAL, "need at least one segment");
+    int r;
+    long long end = h->adj_pos;
+    for (int j = 0; j < nseg; ++j) {
+        if ((r = check_segment(h, slots[j], n, end)) != LBM_OK) return r;
+        end -= n;
+    }
+    if (nseg == 1) return lbm_adjoint_segment(h, slots[0], n);
+    const int np = h->nparts;
+    const size_t cells = (size_t)std::max<long long>(h->cells, 1);
+    if (h->tape2_f.size() != (size_t)h->adj_seg) {
+        // the second tape, as large as the first; where it does not fit the
+        // segments are reversed one after the other
+        free_tape2(h);
+        bool ok = true;
+        h->tape2_f.assign(h->adj_seg, nullptr);
+        for (int t = 0; t < h->adj_seg && ok; ++t) ok = hipMalloc(&h->tape2_f[t], h->buf_bytes) == hipSuccess;
+        ok = ok && hipMalloc((void**)&h->tape2_p, sizeof(PartDev) * (size_t)(h->adj_seg + 1) * std::max(np, 1)) == hipSuccess;
+        ok = ok && hipMalloc((void**)&h->tape2_patch, sizeof(double2) * (size_t)h->adj_seg * cells) == hipSuccess;
+        if (!ok) {
+            free_tape2(h);
+            (void)hipGetLastError();
+            for (int j = 0; j < nseg; ++j)
+                if ((r = lbm_adjoint_segment(h, slots[j], n)) != LBM_OK) return r;
+            return LBM_OK;
+        }
+    }
+    if (!h->stream2) HIPCHK(h, hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
+    for (auto& e : h->tape_ev)
+        if (!e) HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (h->tiles_dirty && (r = build_tiles(h)) != LBM_OK) return r;
+    // clears the flags and waits: the second stream starts after it
+    if ((r = lbm_checkpoint_restore(h, slots[0])) != LBM_OK) return r;
+    const TapeRef T[2] = {{&h->tape_f, h->tape_p, h->tape_patch}, {&h->tape2_f, h->tape2_p, h->tape2_patch}};
+    // Segment j is taped into T[j % 2] on the second stream and reversed
+    // from it on the handle's stream; taping segment j + 1 waits only for
+    // the reversal of segment j - 1 (which read the same tape), so it runs
+    // beside the reversal of segment j.
+    if ((r = tape_segment(h, h->ck[slots[0]], n, T[0], h->stream2)) != LBM_OK) return r;
+    HIPCHK(h, hipEventRecord(h->tape_ev[0], h->stream2));
+    for (int j = 0; j < nseg; ++j) {
+        const int x = j & 1;
+        if (j + 1 < nseg) {
+            if (j >= 1) HIPCHK(h, hipStreamWaitEvent(h->stream2, h->tape_ev[2 + (1 - x)], 0));
+            if ((r = tape_segment(h, h->ck[slots[j + 1]], n, T[1 - x], h->stream2)) != LBM_OK) return r;
+            HIPCHK(h, hipEventRecord(h->tape_ev[1 - x], h->stream2));
+        }
+        HIPCHK(h, hipStreamWaitEvent(h->stream, h->tape_ev[x], 0));
+        if ((r = reverse_segment(h, h->ck[slots[j]], n, T[x], h->stream)) != LBM_OK) return r;
+        HIPCHK(h, hipEventRecord(h->tape_ev[2 + x], h->stream));
+    }
+    // every taping was waited for by a reversal on the handle's stream, so
+    // its synchronisation covers both streams; errors of any segment are
+    // reported here
+    const int rf = check_flags(h);
+    if ((r = lbm_checkpoint_restore(h, slots[nseg - 1])) != LBM_OK) return r;
+    if (rf != LBM_OK) {
+        h->adj_pos = -1;
+        return rf;
+    }
+    h->adj_pos -= (long long)nseg * n;
     return LBM_OK;
 }
 
@@ -1246,7 +1365,11 @@ extern "C" const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c
 extern "C" int lbm_destroy(lbm_handle* h) {
     if (!h) return LBM_OK;
     drop_graphs(h);
+    if (h->stream2) (void)hipStreamSynchronize(h->stream2);
     free_adjoint(h);
+    for (auto& e : h->tape_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->stream2) (void)hipStreamDestroy(h->stream2);
     void* ptrs[] = {h->ws_alloc, h->dchan, h->dtiles, h->dparts, h->dxi, h->dnrm, h->dds, h->dpatch,
                     h->dmscr, h->dflags, h->dtlist, h->dstep, h->drec,
                     h->dwork, h->dpsum, h->dpcount, h->dpartial};

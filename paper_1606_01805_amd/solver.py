@@ -195,6 +195,14 @@ class Solver:
         """Reverse the n steps that start at checkpoint `slot`."""
         self._chk(self._L.lbm_adjoint_segment(self._h, int(slot), int(n)))
 
+    def adjoint_sweep(self, slots, n):
+        """Reverse len(slots) segments of n steps, the last one first: slots[j]
+        is the checkpoint of the j-th segment reversed (bitwise the results
+        of adjoint_segment on each slot in turn; the recomputation of the
+        next segment runs beside the reversal of the current one)."""
+        arr = np.ascontiguousarray(np.asarray(slots, dtype=np.int32))
+        self._chk(self._L.lbm_adjoint_sweep(self._h, arr.ctypes.data_as(ctypes.c_void_p), int(arr.size), int(n)))
+
     @property
     def adjoint_position(self):
         return int(self._L.lbm_adjoint_position(self._h))

@@ -42,7 +42,7 @@ def _case(kind):
     return cfg, [p]
 
 
-def gpu_adjoint(cfg, parts, T, c, seg=None, storage=None, tuning=None):
+def gpu_adjoint(cfg, parts, T, c, seg=None, storage=None, tuning=None, sweep=False, all_parts=False):
     from paper_1606_01805_amd import Solver
 
     seg = seg or T
@@ -50,15 +50,21 @@ def gpu_adjoint(cfg, parts, T, c, seg=None, storage=None, tuning=None):
     for k in range(T // seg):
         s.checkpoint_save(k)
         s.step(seg, record=False)
-    seed = np.zeros((1, 10))
-    seed[0, :6] = c
+    seed = np.zeros((len(parts), 10))
+    seed[:, :6] = c
     s.adjoint_begin(seed, seg)
-    for k in reversed(range(T // seg)):
-        s.adjoint_segment(k, seg)
+    if sweep:
+        s.adjoint_sweep(list(reversed(range(T // seg))), seg)
+    else:
+        for k in reversed(range(T // seg)):
+            s.adjoint_segment(k, seg)
     assert s.adjoint_position == 0
     part, mk, wall = s.adjoint_gradients()
     lam = s.adjoint_field(0)
+    pops = s.populations()
     s.close()
+    if all_parts:
+        return part, mk, wall, lam, pops
     return part[0], mk[0], wall[0], lam
 
 
@@ -331,3 +337,25 @@ def test_batched_multi_particle_adjoint_matches_fd_and_alone():
                 bad.append((ci, j, "xi[3].y", mk[o + j][3, 1], fd))
         o += len(ps)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("storage,overlap", [(C.STORE_F32, 0), (C.STORE_F32, 1), (C.STORE_F64, 0)])
+def test_adjoint_sweep_equals_segments(storage, overlap):
+    """lbm_adjoint_sweep (the next segment recomputed on a second stream
+    beside the reversal of the current one, two tapes) gives bitwise the
+    gradients, adjoint populations and final forward state of
+    lbm_adjoint_segment called segment by segment: five segments, two
+    particles, with and without the combined forward launch."""
+    cfg = C.couette_config(96, 40, storage=storage)
+    parts = [C.particle(shapes.ellipse(10.0, 2.0, n_markers=40), 30.2, 20.4, 0.7),
+             C.particle(shapes.circle(8.0, n_markers=30), 66.8, 17.9, 0.0)]
+    tun = dict(tile_w=64, rows_per_thread=1, overlap=1) if overlap else None
+    c = [0.3, 1.0, 0.2, 0.5, -0.4, 1.0]
+    a = gpu_adjoint(cfg, parts, 150, c, seg=30, storage=storage, tuning=tun, sweep=False, all_parts=True)
+    b = gpu_adjoint(cfg, parts, 150, c, seg=30, storage=storage, tuning=tun, sweep=True, all_parts=True)
+    for x, y in zip(a, b):
+        if isinstance(x, list):
+            for u, v in zip(x, y):
+                assert np.array_equal(u, v)
+        else:
+            assert np.array_equal(x, y)
