@@ -946,30 +946,40 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) 
     // probe stencils (its own box grown by the probe reach), ascending.
     __shared__ int s_nb[kMaxNeighbours];
     __shared__ int s_nnb;
-    if (tid < 64) {
-        // lane j tests particle p_begin + j of each 64-particle chunk; the
-        // ballot keeps the list in ascending order
-        int n = 0;
-        const int grow = (int)ceil(dn) + 2;
-        for (int q0 = c.p_begin; q0 < c.p_end; q0 += 64) {
-            const int q = q0 + tid;
-            bool hit = false;
-            if (q < c.p_end) {
-                const PartDev& Q = a.parts[q];
-                hit = Q.bw > 0 && boxes_overlap(c, P->bx0 - grow, P->by0 - grow, P->bw + 2 * grow,
-                                                P->bh + 2 * grow, Q.bx0, Q.by0, Q.bw, Q.bh);
+    int nnb;
+    if (c.p_end - c.p_begin == 1) {
+        // the channel's only particle: the list is the particle itself
+        // unless the force stage skipped it (its grown box always overlaps
+        // its own box), so no list is built and no barrier is needed; every
+        // thread writes the same entry and reads its own write
+        nnb = skip ? 0 : 1;
+        s_nb[0] = b;
+    } else {
+        if (tid < 64) {
+            // lane j tests particle p_begin + j of each 64-particle chunk; the
+            // ballot keeps the list in ascending order
+            int n = 0;
+            const int grow = (int)ceil(dn) + 2;
+            for (int q0 = c.p_begin; q0 < c.p_end; q0 += 64) {
+                const int q = q0 + tid;
+                bool hit = false;
+                if (q < c.p_end) {
+                    const PartDev& Q = a.parts[q];
+                    hit = Q.bw > 0 && boxes_overlap(c, P->bx0 - grow, P->by0 - grow, P->bw + 2 * grow,
+                                                    P->bh + 2 * grow, Q.bx0, Q.by0, Q.bw, Q.bh);
+                }
+                const unsigned long long bal = __ballot(hit);
+                if (hit) {
+                    const int pos = n + __popcll(bal & ((1ull << tid) - 1ull));
+                    if (pos < kMaxNeighbours) s_nb[pos] = q;
+                }
+                n += __popcll(bal);
             }
-            const unsigned long long bal = __ballot(hit);
-            if (hit) {
-                const int pos = n + __popcll(bal & ((1ull << tid) - 1ull));
-                if (pos < kMaxNeighbours) s_nb[pos] = q;
-            }
-            n += __popcll(bal);
+            if (tid == 0) s_nnb = n;
         }
-        if (tid == 0) s_nnb = n;
+        __syncthreads();
+        nnb = s_nnb;
     }
-    __syncthreads();
-    const int nnb = s_nnb;
 
     if (!skip) {
         if constexpr (kOnePair) {
