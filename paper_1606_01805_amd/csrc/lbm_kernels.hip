@@ -1167,10 +1167,13 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs 
 // The same launch with the vector form of the lattice pass, in 256-thread
 // workgroups: the lattice tiles are those of lattice_vkernel (64 NV x 4
 // nodes), and a particle round runs its 576 (marker, node) pairs on 256
-// threads.  With at most 96 VGPRs and the surface stress's 24 KB of LDS,
-// five such workgroups share a CU, as in lattice_vkernel.
+// threads.  The reduced forms are held to 128 VGPRs (four workgroups per
+// CU beside the surface stress's 24 KB of LDS): at 96 VGPRs, the occupancy
+// of lattice_vkernel in FP32, the surface stress spills 172 bytes per lane,
+// and that scratch traffic costs the lattice pass more than the fifth
+// workgroup gains (ensemble step 387 -> 374 us at 128).
 template <int ST, int NV, bool NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F32 ? 5 : ST == ST_F16S ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 4)))
 void lattice_traction_vkernel(StepArgs a, int tb) {
     const int j = (int)blockIdx.x - tb;
     if (j < 0) {
