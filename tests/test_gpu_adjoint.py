@@ -359,3 +359,28 @@ def test_adjoint_sweep_equals_segments(storage, overlap):
                 assert np.array_equal(u, v)
         else:
             assert np.array_equal(x, y)
+
+
+def test_adjoint_sweep_rejects_bad_schedules():
+    """lbm_adjoint_sweep checks the whole chain of checkpoints before any
+    work: an empty list, a slot out of order or a segment longer than the
+    tape are rejected and leave the adjoint where it was."""
+    from paper_1606_01805_amd import LBMError, Solver
+
+    cfg = C.couette_config(64, 32)
+    parts = [C.particle(shapes.circle(8.0, n_markers=30), 30.2, 15.4, 0.0)]
+    s = Solver([(cfg, parts)])
+    for k in range(3):
+        s.checkpoint_save(k)
+        s.step(10, record=False)
+    s.adjoint_begin(np.ones((1, 10)), 10)
+    with pytest.raises(LBMError, match="EINVAL"):
+        s.adjoint_sweep([], 10)
+    with pytest.raises(LBMError, match="ESTATE"):
+        s.adjoint_sweep([2, 0, 1], 10)  # slot 0 does not end where slot 2 starts
+    with pytest.raises(LBMError, match="EINVAL"):
+        s.adjoint_sweep([2, 1, 0], 11)  # longer than the tape
+    assert s.adjoint_position == 30
+    s.adjoint_sweep([2, 1, 0], 10)
+    assert s.adjoint_position == 0
+    s.close()
