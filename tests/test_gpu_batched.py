@@ -211,3 +211,20 @@ def test_vector_form_coupled_bitwise(storage, tw, overlap):
     assert np.array_equal(g0, g1)
     for a, b in zip(p0, p1):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage,key", [(C.STORE_F32, "huge"), (C.STORE_F16S, "huge16")])
+def test_full_huge_domain_launch_shape_bitwise(storage, key):
+    """The 8192 x 4096 domain with 64 particles in the benchmark's launch
+    shape (vector tiles, nontemporal stores, the surface stress in the same
+    launch) gives bitwise the particle records of the library's default
+    shape (per-node tiles, separate launches) over 10 steps."""
+    from bench import VARIANT_TUNING, make_workload
+
+    wl = make_workload("huge", storage)
+    s, g = run_gpu(wl.channels, 10, tuning=VARIANT_TUNING[key])
+    s.close()
+    s, h = run_gpu(wl.channels, 10)
+    s.close()
+    assert np.isfinite(g).all()
+    assert np.array_equal(g, h)
