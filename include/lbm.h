@@ -167,6 +167,17 @@ typedef struct lbm_tuning {
                                 nontemporally, bypassing the caches; faster
                                 when the two population buffers exceed the
                                 256 MB Infinity Cache, slower when they fit */
+    int32_t adj_fused;       /* launches of a reversed adjoint step when no
+                                channel holds more than one particle.  0: three
+                                (surface stress, immersed boundary, lattice);
+                                1: the two particle kernels as one launch;
+                                2 (default): the whole step as one launch
+                                when its workgroups (the particles, then one
+                                512-thread workgroup per 8 x 64 lattice nodes)
+                                fit the device's compute units at once, else
+                                as 1.  With several particles in a channel
+                                the three launches are used.  Results are
+                                bitwise the same in every form */
 } lbm_tuning;
 
 typedef struct lbm_handle lbm_handle;

@@ -48,7 +48,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("persistent_wgs", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("overlap", ctypes.c_int32), ("vec", ctypes.c_int32),
-                ("nt_store", ctypes.c_int32)]
+                ("nt_store", ctypes.c_int32), ("adj_fused", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); the list mirrors include/lbm.h

@@ -27,6 +27,7 @@
 // atomics), so the adjoint is bitwise reproducible.
 #include <climits>
 
+#include "lbm_adjoint.h"
 #include "lbm_device.h"
 
 namespace lbmk {
@@ -437,23 +438,48 @@ __device__ __forceinline__ void deposit_round(double* apatch, int ax0u, int ay0u
 // per particle, markers in rounds of 64, one thread per (marker, probe
 // stencil node)).
 // ---------------------------------------------------------------------------
+// LDS of the traction part of a reversed step.
+struct AdjTracLds {
+    double w[kAdjThreads], r[kAdjThreads], ux[kAdjThreads], uy[kAdjThreads];
+    double dep[kAdjThreads][3];
+    double S[kAdjThreads][9];  // per node: share of S, then its term
+    double Sm[kAdjRound][9];
+    double B[kAdjRound][6];
+    double sc[kAdjRound][5];   // d/d rho_P, d/d (du/dx, du/dy, dv/dx, dv/dy)
+    double xp[kAdjRound][2];
+    double geo[kAdjRound][4];  // r and n of the marker
+    double g[kAdjRound][5];    // its accumulated shape gradients
+    double pt[kAdjRound][8];   // its particle terms
+    int2 anc[kAdjRound];
+    double part[AL_N], lF[3], run[8];
+    int nb[kMaxNeighbours], nnb;
+    NbBox box[kMaxNeighbours];
+    unsigned long long mask[kAdjMaskCells];
+};
+
 template <int ST>
-__global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
-    __shared__ double s_w[kAdjThreads], s_r[kAdjThreads], s_ux[kAdjThreads], s_uy[kAdjThreads];
-    __shared__ double s_dep[kAdjThreads][3];
-    __shared__ double s_S[kAdjThreads][9];  // per node: share of S, then its term
-    __shared__ double s_Sm[kAdjRound][9];
-    __shared__ double s_B[kAdjRound][6];
-    __shared__ double s_sc[kAdjRound][5];      // d/d rho_P, d/d (du/dx, du/dy, dv/dx, dv/dy)
-    __shared__ double s_xp[kAdjRound][2];
-    __shared__ double s_geo[kAdjRound][4];     // r and n of the marker
-    __shared__ double s_g[kAdjRound][5];       // its accumulated shape gradients
-    __shared__ double s_pt[kAdjRound][8];      // its particle terms
-    __shared__ int2 s_anc[kAdjRound];
-    __shared__ double s_part[AL_N], s_lF[3], s_run[8];
-    __shared__ int s_nb[kMaxNeighbours], s_nnb;
-    __shared__ NbBox s_box[kMaxNeighbours];
-    __shared__ unsigned long long s_mask[kAdjMaskCells];
+__device__ __forceinline__ void adj_traction_body(const AdjArgs& a, AdjTracLds& sh) {
+    auto& s_w = sh.w;
+    auto& s_r = sh.r;
+    auto& s_ux = sh.ux;
+    auto& s_uy = sh.uy;
+    auto& s_dep = sh.dep;
+    auto& s_S = sh.S;
+    auto& s_Sm = sh.Sm;
+    auto& s_B = sh.B;
+    auto& s_sc = sh.sc;
+    auto& s_xp = sh.xp;
+    auto& s_geo = sh.geo;
+    auto& s_g = sh.g;
+    auto& s_pt = sh.pt;
+    auto& s_anc = sh.anc;
+    auto& s_part = sh.part;
+    auto& s_lF = sh.lF;
+    auto& s_run = sh.run;
+    auto& s_nb = sh.nb;
+    auto& s_nnb = sh.nnb;
+    auto& s_box = sh.box;
+    auto& s_mask = sh.mask;
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     if (b >= a.s.nparts) return;
@@ -789,27 +815,56 @@ __global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
     mark_tiles(sa, c, (int)blockIdx.x, ax0u, ay0u, aw, ah, tid, blockDim.x);
 }
 
+template <int ST>
+__global__ __launch_bounds__(kAdjThreads) void adj_traction_kernel(AdjArgs a) {
+    __shared__ AdjTracLds sh;
+    adj_traction_body<ST>(a, sh);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel B: adjoint of the immersed-boundary force and spreading.
 // ---------------------------------------------------------------------------
+// LDS of the immersed-boundary part of a reversed step.
+struct AdjIbmLds {
+    double w[kAdjThreads], usx[kAdjThreads], usy[kAdjThreads];
+    double lfx[kAdjThreads], lfy[kAdjThreads];
+    double dep[kAdjThreads][2];
+    double S[kAdjThreads][9];
+    double Sm[kAdjRound][9];
+    double B[kAdjRound][6];
+    double sc[kAdjRound][5];   // F (2), d/d U (2), c_l
+    double xp[kAdjRound][2];
+    double geo[kAdjRound][2];  // r of the marker
+    double g[kAdjRound][5];    // its accumulated shape gradients
+    double pt[kAdjRound][8];   // its particle terms
+    int2 anc[kAdjRound];
+    double run[8];
+    int nb[kMaxNeighbours];
+    NbBox box[kMaxNeighbours];
+    unsigned long long mask[kAdjMaskCells];
+};
+
 template <int ST>
-__global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
-    __shared__ double s_w[kAdjThreads], s_usx[kAdjThreads], s_usy[kAdjThreads];
-    __shared__ double s_lfx[kAdjThreads], s_lfy[kAdjThreads];
-    __shared__ double s_dep[kAdjThreads][2];
-    __shared__ double s_S[kAdjThreads][9];
-    __shared__ double s_Sm[kAdjRound][9];
-    __shared__ double s_B[kAdjRound][6];
-    __shared__ double s_sc[kAdjRound][5];      // F (2), d/d U (2), c_l
-    __shared__ double s_xp[kAdjRound][2];
-    __shared__ double s_geo[kAdjRound][2];     // r of the marker
-    __shared__ double s_g[kAdjRound][5];       // its accumulated shape gradients
-    __shared__ double s_pt[kAdjRound][8];      // its particle terms
-    __shared__ int2 s_anc[kAdjRound];
-    __shared__ double s_run[8];
-    __shared__ int s_nb[kMaxNeighbours];
-    __shared__ NbBox s_box[kMaxNeighbours];
-    __shared__ unsigned long long s_mask[kAdjMaskCells];
+__device__ __forceinline__ void adj_ibm_body(const AdjArgs& a, AdjIbmLds& sh) {
+    auto& s_w = sh.w;
+    auto& s_usx = sh.usx;
+    auto& s_usy = sh.usy;
+    auto& s_lfx = sh.lfx;
+    auto& s_lfy = sh.lfy;
+    auto& s_dep = sh.dep;
+    auto& s_S = sh.S;
+    auto& s_Sm = sh.Sm;
+    auto& s_B = sh.B;
+    auto& s_sc = sh.sc;
+    auto& s_xp = sh.xp;
+    auto& s_geo = sh.geo;
+    auto& s_g = sh.g;
+    auto& s_pt = sh.pt;
+    auto& s_anc = sh.anc;
+    auto& s_run = sh.run;
+    auto& s_nb = sh.nb;
+    auto& s_box = sh.box;
+    auto& s_mask = sh.mask;
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     if (b >= a.s.nparts) return;
@@ -1042,6 +1097,30 @@ __global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
     }
 }
 
+template <int ST>
+__global__ __launch_bounds__(kAdjThreads) void adj_ibm_kernel(AdjArgs a) {
+    __shared__ AdjIbmLds sh;
+    adj_ibm_body<ST>(a, sh);
+}
+
+// Kernels A and B as one launch, for handles whose channels hold at most one
+// particle each.  A particle alone in its channel has no neighbour, so
+// everything its IB part reads from the traction part (the probe terms of its
+// adjoint patch, its adjoint box and neighbour list, the marker gradients and
+// the particle adjoint) was written by its own workgroup before the barrier.
+// The arithmetic and its order are those of the two launches; the LDS is
+// shared between the parts.
+template <int ST>
+__global__ __launch_bounds__(kAdjThreads) void adj_particle_kernel(AdjArgs a) {
+    __shared__ union {
+        AdjTracLds t;
+        AdjIbmLds i;
+    } sh;
+    adj_traction_body<ST>(a, sh.t);
+    __syncthreads();
+    adj_ibm_body<ST>(a, sh.i);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel C: the adjoint lattice pass.
 // ---------------------------------------------------------------------------
@@ -1060,13 +1139,135 @@ __device__ __forceinline__ long long wall_slot(const AdjArgs& a, int chan, const
     return -1;
 }
 
+// Density and velocities of a node: rho, u = (j + f/2)/rho and u* = j/rho.
+struct NodeVel {
+    double rho, ux, uy, usx, usy;
+};
+
+// Moments of node (x, y) from its raw pulled populations fr, with the walls
+// applied on load.
+__device__ __forceinline__ void adj_node_moments(const ChanDev& c, int x, int y, const double fr[9], double& rho,
+                                                 double& jx, double& jy) {
+    double f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = fr[i];
+    walls_f64(c, c, x, y, f);
+    moments_f64(f, c, rho, jx, jy);
+}
+
+__device__ __forceinline__ NodeVel node_vel(double rho, double jx, double jy, double fx, double fy) {
+    NodeVel v;
+    v.rho = rho;
+    v.ux = (jx + 0.5 * fx) / rho;
+    v.uy = (jy + 0.5 * fy) / rho;
+    v.usx = jx / rho;
+    v.usy = jy / rho;
+    return v;
+}
+
+// The rest of the adjoint lattice update of node (x, y) of channel ch, from
+// its raw pulled populations fr, its density and velocities, the adjoint
+// populations L pushed to it (overwritten), the force (fx, fy) and the
+// adjoint patch terms tt: the transposes of the collision and of the
+// moments, and on wall nodes of the Zou-He closure; stores the node's
+// adjoint populations.
+template <int ST>
+__device__ __forceinline__ void adj_node_finish(const AdjArgs& a, const ChanDev& c, int ch, int x, int y,
+                                                const double fr[9], const NodeVel& v, double L[9], double fx,
+                                                double fy, const double tt[kAdjCell]) {
+    using LT = typename LamT<ST>::T;
+    LT* __restrict__ lout = (LT*)a.lam_out;
+    const double rho = v.rho, ux = v.ux, uy = v.uy, usx = v.usx, usy = v.usy;
+    const CollAdj ca = collide_adj(L, rho, ux, uy, c.g[0] + fx, c.g[1] + fy, c.tau);
+    // u = (j + f_lb/2)/rho, u* = j/rho, rho = sum f, j = sum f e + g/2
+    const double lux = ca.lux + tt[1], luy = ca.luy + tt[2];
+    const double ljx = (lux + tt[3]) / rho, ljy = (luy + tt[4]) / rho;
+    const double lrho = ca.lrho + tt[0] - (lux * ux + luy * uy) / rho - (tt[3] * usx + tt[4] * usy) / rho;
+    const double keep = 1.0 - 1.0 / c.tau;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) L[i] = keep * L[i] + lrho + ljx * (double)ex(i) + ljy * (double)ey(i);
+    int side = -1;
+    const long long ws = wall_slot(a, ch, c, x, y, side);
+    if (ws >= 0) {
+        double gux = 0.0, guy = 0.0;
+        // wall velocity by branches: a runtime index into the channel
+        // descriptor would move it to scratch memory
+        const double uwx = side == 0 ? c.uw[0][0] : (side == 1 ? c.uw[1][0] : (side == 2 ? c.uw[2][0] : c.uw[3][0]));
+        const double uwy = side == 0 ? c.uw[0][1] : (side == 1 ? c.uw[1][1] : (side == 2 ? c.uw[2][1] : c.uw[3][1]));
+        zouhe_adj(side, fr, L, uwx, uwy, c.g[0], c.g[1], gux, guy);
+        a.gwall[ws] += gux;
+        a.gwall[ws + 1] += guy;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lout[pidx(c, i, y, x)] = (LT)L[i];
+}
+
+// The adjoint lattice update of node (x, y) of channel ch: adjoint
+// streaming (the pushes of the next step's adjoint populations) and the
+// force and adjoint patch terms of the listed particles (ascending), then
+// adj_node_finish.
+template <int ST>
+__device__ __forceinline__ void adj_node(const AdjArgs& a, const ChanDev& c, int ch, const int* list, int nlist,
+                                         int x, int y) {
+    double fr[9];
+    pull_raw_f64<ST>(a.s.fin, c, x, y, fr);
+    double rho, jx, jy;
+    adj_node_moments(c, x, y, fr, rho, jx, jy);
+    double fx = 0.0, fy = 0.0, tt[kAdjCell] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (nlist > 0) patch_terms<kAdjCell>(a, c, list, nlist, x, y, fx, fy, tt);
+    const NodeVel v = node_vel(rho, jx, jy, fx, fy);
+    double L[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) L[i] = lam_push<ST>(a.lam_in, c, i, x, y);
+    adj_node_finish<ST>(a, c, ch, x, y, fr, v, L, fx, fy, tt);
+}
+
+// The loads of one node of a particle's own adjoint box (cell q of the box),
+// issued together: its pulled populations, the adjoint populations pushed
+// to it, and its cells of the particle's force and adjoint patches, whose
+// boxes are known.  The values and their sums are those of adj_node with
+// the particle as the only listed one (patch_terms starts from zero and adds
+// only inside a box).
+struct BoxNode {
+    int x, y;
+    bool ok;
+    double fr[9], L[9], fx, fy, tt[kAdjCell];
+};
+
+template <int ST>
+__device__ __forceinline__ void box_node_load(const AdjArgs& a, const ChanDev& c, const PartDev& P,
+                                              const AdjPart& A, int q, BoxNode& n) {
+    int x = A.ax0 + q % A.aw, y = A.ay0 + q / A.aw;
+    if (c.bcx == 0 && x >= c.nx) x -= c.nx;
+    if (c.bcy == 0 && y >= c.ny) y -= c.ny;
+    n.ok = x >= 0 && x < c.nx && y >= 0 && y < c.ny;
+    // a node outside the channel reads node 0 and is not stored
+    n.x = n.ok ? x : 0;
+    n.y = n.ok ? y : 0;
+    pull_raw_f64<ST>(a.s.fin, c, n.x, n.y, n.fr);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) n.L[i] = lam_push<ST>(a.lam_in, c, i, n.x, n.y);
+    const int cf = P.bw > 0 ? box_cell(c, P.bx0, P.by0, P.bw, P.bh, n.x, n.y) : -1;
+    const double2 v = a.s.patch[P.patch_off + (cf >= 0 ? cf : 0)];
+    n.fx = 0.0;
+    n.fy = 0.0;
+    if (cf >= 0) {
+        n.fx += v.x;
+        n.fy += v.y;
+    }
+    const double* va = a.apatch + (A.aoff + q) * kAdjCell;
+#pragma unroll
+    for (int k = 0; k < kAdjCell; ++k) {
+        n.tt[k] = 0.0;
+        n.tt[k] += va[k];
+    }
+}
+
 // One wave per 64-node chunk of a tile (chunks = tile nodes / 64): the
 // forward tile table and its particle lists are reused, and small lattices
 // still spread over many compute units.
 template <int ST>
 __global__ __launch_bounds__(64) void adj_lattice_kernel(AdjArgs a, int tw, int chunks) {
-    using LT = typename LamT<ST>::T;
-    LT* __restrict__ lout = (LT*)a.lam_out;
     const int t = blockIdx.x / chunks, part = blockIdx.x % chunks;
     if (t >= a.s.ntiles) return;
     const int* tl_cur = a.atlist + (long long)a.s.parity * a.s.ntiles * kTileList;
@@ -1097,47 +1298,91 @@ __global__ __launch_bounds__(64) void adj_lattice_kernel(AdjArgs a, int tw, int 
     }
     const int node = part * 64 + (int)threadIdx.x;
     const int x = tx0 + node % tw, y = ty0 + node / tw;
-    if (x < c.nx && y < c.ny) {
-        double fr[9], f[9];
-        pull_raw_f64<ST>(a.s.fin, c, x, y, fr);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = fr[i];
-        walls_f64(c, c, x, y, f);
-        double rho, jx, jy;
-        moments_f64(f, c, rho, jx, jy);
-        double fx = 0.0, fy = 0.0, tt[kAdjCell] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (nlist > 0) patch_terms<kAdjCell>(a, c, list, nlist, x, y, fx, fy, tt);
-        const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho;
-        const double usx = jx / rho, usy = jy / rho;
-        double L[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) L[i] = lam_push<ST>(a.lam_in, c, i, x, y);
-        const CollAdj ca = collide_adj(L, rho, ux, uy, c.g[0] + fx, c.g[1] + fy, c.tau);
-        // u = (j + f_lb/2)/rho, u* = j/rho, rho = sum f, j = sum f e + g/2
-        const double lux = ca.lux + tt[1], luy = ca.luy + tt[2];
-        const double ljx = (lux + tt[3]) / rho, ljy = (luy + tt[4]) / rho;
-        const double lrho = ca.lrho + tt[0] - (lux * ux + luy * uy) / rho - (tt[3] * usx + tt[4] * usy) / rho;
-        const double keep = 1.0 - 1.0 / c.tau;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) L[i] = keep * L[i] + lrho + ljx * (double)ex(i) + ljy * (double)ey(i);
-        int side = -1;
-        const long long ws = wall_slot(a, ch, c, x, y, side);
-        if (ws >= 0) {
-            double gux = 0.0, guy = 0.0;
-            // wall velocity by branches: a runtime index into the channel
-            // descriptor would move it to scratch memory
-            const double uwx = side == 0 ? c.uw[0][0] : (side == 1 ? c.uw[1][0] : (side == 2 ? c.uw[2][0] : c.uw[3][0]));
-            const double uwy = side == 0 ? c.uw[0][1] : (side == 1 ? c.uw[1][1] : (side == 2 ? c.uw[2][1] : c.uw[3][1]));
-            zouhe_adj(side, fr, L, uwx, uwy, c.g[0], c.g[1], gux, guy);
-            a.gwall[ws] += gux;
-            a.gwall[ws + 1] += guy;
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) lout[pidx(c, i, y, x)] = (LT)L[i];
-    }
+    if (x < c.nx && y < c.ny) adj_node<ST>(a, c, ch, list, nlist, x, y);
     // reset the other parity's list (read by no kernel of this step) for the
     // next reverse step
     if (part == 0 && threadIdx.x == 0) tl_next[(long long)t * kTileList] = 0;
+}
+
+// A whole reversed step as one launch, for handles whose channels hold at
+// most one particle each and whose lattice is small enough that the launch
+// is latency-bound.  The first nparts workgroups run the two particle
+// kernels (as adj_particle_kernel) and then the adjoint lattice update of
+// the nodes of their own adjoint box, whose patch terms they have just
+// written.  The other workgroups take the 64-node chunks of the tiles, one
+// wave each, from the start and skip the nodes of that box.  They find the
+// box from the particle's taped state with the surface-stress part's own
+// test, not from the adjoint state being written beside them.  The force
+// patch lies inside the adjoint box (same centre, shorter reach), so a node
+// outside it has neither force nor adjoint patch terms: the update of every
+// node is bitwise that of adj_lattice_kernel.
+template <int ST>
+__global__ __launch_bounds__(kAdjThreads) void adj_step_kernel(AdjArgs a, int tw, int chunks) {
+    __shared__ union {
+        AdjTracLds t;
+        AdjIbmLds i;
+    } sh;
+    const int b = blockIdx.x;
+    if (b < a.s.nparts) {
+        adj_traction_body<ST>(a, sh.t);
+        __syncthreads();
+        adj_ibm_body<ST>(a, sh.i);
+        __syncthreads();
+        // the nodes of the particle's adjoint box (aw = 0: none), two per
+        // thread with all their loads issued before either's arithmetic
+        const PartDev& P = a.s.parts[b];
+        const AdjPart& A = a.ap[b];
+        const int ch = P.chan;
+        const ChanDev c = load_chan(a.s.chan + ch);
+        const int ncell = A.aw * A.ah;
+        for (int q = threadIdx.x; q < ncell; q += 2 * kAdjThreads) {
+            const bool two = q + kAdjThreads < ncell;
+            BoxNode n0, n1;
+            box_node_load<ST>(a, c, P, A, q, n0);
+            if (two) box_node_load<ST>(a, c, P, A, q + kAdjThreads, n1);
+            if (n0.ok) {
+                double rho, jx, jy;
+                adj_node_moments(c, n0.x, n0.y, n0.fr, rho, jx, jy);
+                const NodeVel v = node_vel(rho, jx, jy, n0.fx, n0.fy);
+                adj_node_finish<ST>(a, c, ch, n0.x, n0.y, n0.fr, v, n0.L, n0.fx, n0.fy, n0.tt);
+            }
+            if (two && n1.ok) {
+                double rho, jx, jy;
+                adj_node_moments(c, n1.x, n1.y, n1.fr, rho, jx, jy);
+                const NodeVel v = node_vel(rho, jx, jy, n1.fx, n1.fy);
+                adj_node_finish<ST>(a, c, ch, n1.x, n1.y, n1.fr, v, n1.L, n1.fx, n1.fy, n1.tt);
+            }
+        }
+        return;
+    }
+    const int gc = (b - a.s.nparts) * (kAdjThreads / 64) + (int)threadIdx.x / 64;
+    const int t = gc / chunks, part = gc % chunks;
+    if (t >= a.s.ntiles) return;
+    int* tl_next = a.atlist + (long long)(1 - a.s.parity) * a.s.ntiles * kTileList;
+    const TileDev* tp = a.s.tiles + t;
+    const int tx0 = uni(tp->x0), ty0 = uni(tp->y0), ch = uni(tp->chan);
+    const ChanDev c = load_chan(a.s.chan + ch);
+    int bx0 = 0, by0 = 0, bw = 0, bh = 0;
+    if (c.p_end > c.p_begin) {
+        const int q = c.p_begin;
+        const PartDev* P = a.s.parts + q;
+        int ax0u, ay0u, aw, ah;
+        stencil_box(P->X[0], P->X[1], P->rb + c.dn, ax0u, ay0u, aw, ah);
+        if ((long long)aw * ah <= a.ap[q].acap && aw <= c.nx && ah <= c.ny) {
+            bx0 = wrapc(ax0u, c.nx, c.bcx == 0);
+            by0 = wrapc(ay0u, c.ny, c.bcy == 0);
+            bw = aw;
+            bh = ah;
+        }
+    }
+    const int node = part * 64 + (int)threadIdx.x % 64;
+    const int x = tx0 + node % tw, y = ty0 + node / tw;
+    if (x < c.nx && y < c.ny && box_cell(c, bx0, by0, bw, bh, x, y) < 0)
+        adj_node<ST>(a, c, ch, nullptr, 0, x, y);
+    // reset the other parity's list for the next reverse step, as
+    // adj_lattice_kernel does (the surface-stress part still fills this
+    // step's list, so the two launch forms can follow each other)
+    if (part == 0 && threadIdx.x % 64 == 0) tl_next[(long long)t * kTileList] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1238,6 +1483,14 @@ hipError_t launch_adj_ibm(int store, const AdjArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_adj_particle(int store, const AdjArgs& a, hipStream_t s) {
+    if (a.s.nparts <= 0) return hipSuccess;
+#define L_(ST) adj_particle_kernel<ST><<<a.s.nparts, kAdjThreads, 0, s>>>(a)
+    ADJ_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_lattice(int store, const AdjArgs& a, hipStream_t s) {
     // one 64-node chunk per workgroup; tile widths are multiples of 64
     if (a.s.tile_w % 64 != 0 || a.s.tile_h < 1) return hipErrorInvalidValue;
@@ -1246,6 +1499,24 @@ hipError_t launch_adj_lattice(int store, const AdjArgs& a, hipStream_t s) {
     if (grid <= 0) return hipSuccess;
     if (grid > INT_MAX) return hipErrorInvalidValue;
 #define L_(ST) adj_lattice_kernel<ST><<<(int)grid, 64, 0, s>>>(a, a.s.tile_w, chunks)
+    ADJ_DISPATCH(store, L_)
+#undef L_
+    return hipGetLastError();
+}
+
+int adj_step_workgroups(const AdjArgs& a) {
+    if (a.s.tile_w % 64 != 0 || a.s.tile_h < 1) return -1;
+    const long long chunks = (long long)a.s.ntiles * (a.s.tile_w / 64 * a.s.tile_h);
+    const long long g = a.s.nparts + (chunks + kAdjThreads / 64 - 1) / (kAdjThreads / 64);
+    return g > INT_MAX ? -1 : (int)g;
+}
+
+hipError_t launch_adj_step(int store, const AdjArgs& a, hipStream_t s) {
+    const int grid = adj_step_workgroups(a);
+    if (grid < 0) return hipErrorInvalidValue;
+    if (grid == 0) return hipSuccess;
+    const int chunks = a.s.tile_w / 64 * a.s.tile_h;
+#define L_(ST) adj_step_kernel<ST><<<grid, kAdjThreads, 0, s>>>(a, a.s.tile_w, chunks)
     ADJ_DISPATCH(store, L_)
 #undef L_
     return hipGetLastError();

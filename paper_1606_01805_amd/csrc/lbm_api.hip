@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_adjoint.h"
 #include "lbm_internal.h"
 
 using namespace lbmk;
@@ -91,7 +92,8 @@ struct lbm_handle {
     ChanDev* dchan = nullptr;
     std::vector<TileDev> htiles;
     TileDev* dtiles = nullptr;
-    lbm_tuning tune{256, 1, 0, 1, 1, 0, 0, 0};
+    lbm_tuning tune{256, 1, 0, 1, 1, 0, 0, 0, 2};
+    int cus = 256;                 // compute units of the device
     bool tiles_dirty = true;
     std::vector<PartHost> parts;
     std::vector<int> dev_of_user;  // user particle id -> device index
@@ -113,6 +115,7 @@ struct lbm_handle {
     long long* dstep = nullptr;
     double* drec = nullptr;
     int nparts = 0;
+    bool alone = true;             // no channel holds more than one particle
     int max_cells = kMaxCells;
     int cur = 0;
     long long steps = 0;
@@ -370,6 +373,12 @@ extern "C" int lbm_init(const lbm_channel_config* cfg, int32_t n, void* stream, 
             FAIL((lbm_handle*)nullptr, LBM_EDEVICE, "address of the staging array: %s", hipGetErrorString(e));
         }
     }
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            h->cus = ncu;
+    }
     h->cfg.assign(cfg, cfg + n);
     h->store = cfg[0].storage;
     h->elem = elem_size(h->store);
@@ -546,6 +555,8 @@ static int finalize(lbm_handle* h) {
     }
     h->nparts = np;
     h->cells = cells;
+    h->alone = true;
+    for (const auto& ch : h->hchan) h->alone = h->alone && ch.p_end - ch.p_begin <= 1;
     const size_t nmk = std::max<size_t>(ds.size(), 1);
     HIPCHK(h, hipMalloc(&h->dparts, sizeof(PartDev) * std::max(np, 1)));
     HIPCHK(h, hipMalloc(&h->dxi, sizeof(double2) * nmk));
@@ -885,6 +896,7 @@ extern "C" int lbm_set_tuning(lbm_handle* h, const lbm_tuning* t) {
     if (t->use_graph != 0 && t->use_graph != 1) FAIL(h, LBM_EINVAL, "use_graph must be 0 or 1");
     if (t->xcd_remap != 0 && t->xcd_remap != 1) FAIL(h, LBM_EINVAL, "xcd_remap must be 0 or 1");
     if (t->overlap != 0 && t->overlap != 1) FAIL(h, LBM_EINVAL, "overlap must be 0 or 1");
+    if (t->adj_fused < 0 || t->adj_fused > 2) FAIL(h, LBM_EINVAL, "adj_fused must be 0, 1 or 2");
     if (t->overlap && !t->vec && (t->tile_w != 64 || t->persistent_wgs != 0))
         FAIL(h, LBM_EINVAL, "overlap = 1 needs tile_w = 64 and persistent_wgs = 0");
     const bool tiles = t->tile_w != h->tune.tile_w || tile_height(*t) != tile_height(h->tune);
@@ -1153,9 +1165,21 @@ static int reverse_segment(lbm_handle* h, const Checkpoint& ck, int n, const Tap
         a.s.patch = T.patch + (size_t)t * cells;
         a.pnext = T.p + (size_t)(t + 1) * np;
         a.first = h->adj_first ? 1 : 0;
-        HIPCHK(h, launch_adj_traction(h->store, a, s));
-        HIPCHK(h, launch_adj_ibm(h->store, a, s));
-        HIPCHK(h, launch_adj_lattice(h->store, a, s));
+        // channels of at most one particle: the particle kernels as one
+        // launch, and with a lattice whose chunks fit the CUs in one pass
+        // (a latency-bound step) the adjoint lattice pass in it too
+        const int wgs = h->tune.adj_fused == 2 && h->alone ? adj_step_workgroups(a) : -1;
+        if (wgs >= 0 && wgs <= h->cus) {
+            HIPCHK(h, launch_adj_step(h->store, a, s));
+        } else {
+            if (h->tune.adj_fused && h->alone) {
+                HIPCHK(h, launch_adj_particle(h->store, a, s));
+            } else {
+                HIPCHK(h, launch_adj_traction(h->store, a, s));
+                HIPCHK(h, launch_adj_ibm(h->store, a, s));
+            }
+            HIPCHK(h, launch_adj_lattice(h->store, a, s));
+        }
         h->lcur = 1 - h->lcur;
         h->apar = 1 - h->apar;
         h->adj_first = false;

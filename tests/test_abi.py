@@ -38,7 +38,7 @@ def test_binding_struct_layouts_match_header():
     # + 2 int + 3 double + 2 int
     assert ctypes.sizeof(_lib.ChannelConfig) == 4 * 2 + 8 + 4 * 2 + 64 + 8 + 32 + 8 + 24 + 8
     assert ctypes.sizeof(_lib.ParticleDesc) == 9 * 8 + 8 + 3 * 8
-    assert ctypes.sizeof(_lib.Tuning) == 32
+    assert ctypes.sizeof(_lib.Tuning) == 9 * 4
 
 
 def _cfg(**kw):

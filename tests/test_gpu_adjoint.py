@@ -339,6 +339,58 @@ def test_batched_multi_particle_adjoint_matches_fd_and_alone():
     assert not bad, bad
 
 
+@pytest.mark.parametrize("storage", [C.STORE_F64, C.STORE_F32, C.STORE_F16S])
+def test_fused_adjoint_launches_bitwise(storage):
+    """When no channel holds more than one particle, a reversed step runs its
+    two particle kernels as one launch (adj_fused = 1), or the whole step,
+    lattice included, as one launch (adj_fused = 2, the default, used when
+    its workgroups fit the device at once, as here).  Gradients and adjoint
+    populations are bitwise those of the three launches (adj_fused = 0):
+    four channels of one particle each, one of them of 120 markers (three
+    rounds of 56 in the adjoint kernels), one with side walls, gravity and a
+    body force, one whose particle straddles the periodic seam (its adjoint
+    box wraps)."""
+    from paper_1606_01805_amd import Solver
+
+    ch0 = C.couette_config(64, 40, tau=0.8, storage=0)
+    ch0["gravity"] = [0.0, -2e-6]
+    ch1 = C.couette_config(48, 30, tau=0.7, storage=0)
+    ch2 = C.base_config(24, 32, tau=0.8, bc_x=1, u_wall=[[0.0, 0.01], [0.0, -0.02], [0.0, 0.0], [0.0, 0.0]],
+                        body_force=[0.0, 1e-5], storage=0)
+    ch3 = C.couette_config(40, 28, tau=0.9, storage=0)
+    chans = [(ch0, [C.particle(shapes.ellipse(16.0, 2.0, n_markers=120, mode="param"), 30.3, 19.6, 0.4,
+                               density_ratio=1.2, u=0.001)]),
+             (ch1, [C.particle(shapes.circle(8.0, n_markers=30), 20.6, 15.2, 0.0, density_ratio=1.1, v=0.0005)]),
+             (ch2, [C.particle(shapes.square(7.0), 11.7, 16.4, 0.1, density_ratio=1.3, omega=0.001)]),
+             (ch3, [C.particle(shapes.ellipse(8.0, 2.0, n_markers=20, mode="param"), 1.4, 13.8, 0.3,
+                               density_ratio=1.1, u=0.002)])]
+    T = 12
+    seeds = np.zeros((len(chans), 10))
+    seeds[:, :6] = np.random.default_rng(31).standard_normal((len(chans), 6))
+
+    def run(mode):
+        s = Solver(chans, storage=storage, tuning=dict(adj_fused=mode))
+        assert s.tuning()["adj_fused"] == mode
+        s.checkpoint_save(0)
+        s.step(T, record=False)
+        s.adjoint_begin(seeds, T)
+        s.adjoint_segment(0, T)
+        part, mk, wall = s.adjoint_gradients()
+        lam = [s.adjoint_field(ci) for ci in range(len(chans))]
+        s.close()
+        return part, mk, wall, lam
+
+    ref = run(0)
+    assert np.all(np.isfinite(ref[0])) and np.any(ref[0] != 0.0)
+    for mode in (1, 2):
+        got = run(mode)
+        assert np.array_equal(got[0], ref[0]), mode
+        for j in range(len(chans)):
+            assert np.array_equal(got[1][j], ref[1][j]), (mode, j)
+            assert np.array_equal(got[2][j], ref[2][j]), (mode, j)
+            assert np.array_equal(got[3][j], ref[3][j]), (mode, j)
+
+
 @pytest.mark.parametrize("storage,overlap", [(C.STORE_F32, 0), (C.STORE_F32, 1), (C.STORE_F64, 0)])
 def test_adjoint_sweep_equals_segments(storage, overlap):
     """lbm_adjoint_sweep (the next segment recomputed on a second stream

@@ -271,7 +271,7 @@ def test_vector_form_rejects_bad_shapes():
     for bad in (dict(vec=1, tile_w=512), dict(vec=1, tile_w=256, rows_per_thread=4),
                 dict(vec=1, tile_w=256, overlap=1, persistent_wgs=64),
                 dict(vec=1, tile_w=256, rows_per_thread=2, overlap=1),
-                dict(vec=2), dict(vec=0, nt_store=1)):
+                dict(vec=2), dict(vec=0, nt_store=1), dict(adj_fused=3), dict(adj_fused=-1)):
         with pytest.raises(LBMError, match="EINVAL"):
             s.set_tuning(**bad)
     s.close()
