@@ -380,6 +380,21 @@ __device__ __forceinline__ void mls_term(const ChanDev& c, const double* S9, con
 // store); a cell is handled by the same thread in every round.  The first
 // round writes the cell (and zeroes fields NZ.. when NZ < kAdjCell), later
 // rounds add to it.
+// acc + v[0][e] + v[1][e] + ... + v[n - 1][e], added in that order, with the
+// LDS reads issued eight at a time instead of one per add.
+__device__ __forceinline__ double ordered_sum8(double acc, const double (*v)[8], int n, int e) {
+    int m = 0;
+    for (; m + 8 <= n; m += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = v[m + u][e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u];
+    }
+    for (; m < n; ++m) acc += v[m][e];
+    return acc;
+}
+
 template <int NF, int F0, int W, int NZ>
 __device__ __forceinline__ void deposit_round(double* apatch, int ax0u, int ay0u, int aw, int ah, int ncell,
                                               const int2* anc, const unsigned long long* mask,
@@ -547,7 +562,24 @@ __device__ __forceinline__ void adj_traction_body(const AdjArgs& a, AdjTracLds& 
     if (!fits) return;
     // neighbours: particles of the channel whose adjoint boxes overlap ours
     // (their force patches lie inside their adjoint boxes)
-    if (tid < 64) {
+    if (tid < 64 && c.p_end - c.p_begin == 1) {
+        // alone in its channel: the list is the particle itself (its box
+        // overlaps itself), with no scan
+        if (tid == 0) {
+            s_nb[0] = b;
+            NbBox& B = s_box[0];
+            B.fx0 = P->bx0;
+            B.fy0 = P->by0;
+            B.fw = P->bw > 0 ? P->bw : 0;
+            B.fh = P->bh;
+            B.foff = P->patch_off;
+            B.ax0 = B.ay0 = B.aw = B.ah = 0;
+            B.aoff = 0;
+            s_nnb = 1;
+            A->nnb = 1;
+            A->nb[0] = b;
+        }
+    } else if (tid < 64) {
         int n = 0;
         for (int q0 = c.p_begin; q0 < c.p_end; q0 += 64) {
             const int q = q0 + tid;
@@ -789,12 +821,7 @@ __device__ __forceinline__ void adj_traction_body(const AdjArgs& a, AdjTracLds& 
         // clear the round's anchor bits; running per-particle sums over the
         // markers, ascending
         if (act && k == 0 && ncell <= kAdjMaskCells) s_mask[(s_anc[lo].y - ay0u) * aw + (s_anc[lo].x - ax0u)] = 0ull;
-        if (tid < 7) {
-            const int nr = min(kAdjRound, nm - r0);
-            double acc = s_run[tid];
-            for (int m = 0; m < nr; ++m) acc += s_pt[m][tid];
-            s_run[tid] = acc;
-        }
+        if (tid < 7) s_run[tid] = ordered_sum8(s_run[tid], s_pt, min(kAdjRound, nm - r0), tid);
         __syncthreads();
     }
     if (tid == 0) {
@@ -876,14 +903,17 @@ __device__ __forceinline__ void adj_ibm_body(const AdjArgs& a, AdjIbmLds& sh) {
     const double X0 = P->X[0], X1 = P->X[1];
     const double Om = P->Om, V0 = P->V[0], V1 = P->V[1];
     const double cs = P->cth, sn = P->sth;
-    const int nnb = A->nnb;
+    // alone in its channel, the surface-stress part listed only the
+    // particle itself: no dependent read of that list
+    const bool alone = c.p_end - c.p_begin == 1;
+    const int nnb = alone ? 1 : A->nnb;
     // marker geometry of the first round, requested early
     double2 pre_x = make_double2(0.0, 0.0);
     if (tid / 9 < kAdjRound && tid / 9 < nm) pre_x = a.s.xi[mb + tid / 9];
     if (tid < kMaxNeighbours) {
-        s_nb[tid] = A->nb[tid];
+        const int q = alone ? b : A->nb[tid];
+        s_nb[tid] = q;
         if (tid < nnb) {
-            const int q = A->nb[tid];
             const PartDev& Q = a.s.parts[q];
             const AdjPart& QA = a.ap[q];
             NbBox& B = s_box[tid];
@@ -1078,12 +1108,7 @@ __device__ __forceinline__ void adj_ibm_body(const AdjArgs& a, AdjIbmLds& sh) {
         }
         __syncthreads();
         if (act && k == 0 && ncell <= kAdjMaskCells) s_mask[(s_anc[lo].y - ay0u) * aw + (s_anc[lo].x - ax0u)] = 0ull;
-        if (tid < 6) {
-            const int nr = min(kAdjRound, nm - r0);
-            double acc = s_run[tid];
-            for (int m = 0; m < nr; ++m) acc += s_pt[m][tid];
-            s_run[tid] = acc;
-        }
+        if (tid < 6) s_run[tid] = ordered_sum8(s_run[tid], s_pt, min(kAdjRound, nm - r0), tid);
         __syncthreads();
     }
     if (tid == 0) {
