@@ -116,6 +116,8 @@ struct lbm_handle {
     double* drec = nullptr;
     int nparts = 0;
     bool alone = true;             // no channel holds more than one particle
+    int tape_np = -1;              // particles and patch cells the tapes were sized for
+    long long tape_cells = -1;
     int max_cells = kMaxCells;
     int cur = 0;
     long long steps = 0;
@@ -984,17 +986,24 @@ static void free_tape2(lbm_handle* h) {
     h->tape2_patch = nullptr;
 }
 
-static void free_adjoint(lbm_handle* h) {
+// Both tapes of the adjoint.
+static void free_tapes(lbm_handle* h) {
     free_tape2(h);
     for (void* p : h->tape_f)
         if (p) (void)hipFree(p);
     h->tape_f.clear();
-    void* ptrs[] = {h->tape_p, h->tape_patch, h->lam[0], h->dap, h->dapatch, h->dgmk,
-                    h->dgwall, h->dgwoff, h->datlist, h->dgout};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    if (h->tape_p) (void)hipFree(h->tape_p);
+    if (h->tape_patch) (void)hipFree(h->tape_patch);
     h->tape_p = nullptr;
     h->tape_patch = nullptr;
+    h->tape_np = -1;
+    h->tape_cells = -1;
+}
+// The adjoint state other than the tapes.
+static void free_adjoint_state(lbm_handle* h) {
+    void* ptrs[] = {h->lam[0], h->dap, h->dapatch, h->dgmk, h->dgwall, h->dgwoff, h->datlist, h->dgout};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
     h->lam[0] = h->lam[1] = nullptr;
     h->dap = nullptr;
     h->dapatch = nullptr;
@@ -1003,6 +1012,10 @@ static void free_adjoint(lbm_handle* h) {
     h->datlist = nullptr;
     h->adj_seg = 0;
     h->adj_pos = -1;
+}
+static void free_adjoint(lbm_handle* h) {
+    free_tapes(h);
+    free_adjoint_state(h);
 }
 
 static AdjArgs adj_args(lbm_handle* h) {
@@ -1072,7 +1085,10 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
         const size_t nwall = cf.bc_y == LBM_BC_ZOUHE ? 2 * (size_t)cf.nx : (cf.bc_x == LBM_BC_ZOUHE ? 2 * (size_t)cf.ny : 0);
         gw += 2 * nwall + (size_t)cf.ny;
     }
-    free_adjoint(h);
+    // the tapes of a previous adjoint of the same length and particle set
+    // are kept: every tape slot is written before it is read
+    free_adjoint_state(h);
+    if (h->tape_f.size() != (size_t)max_segment || h->tape_np != np || h->tape_cells != h->cells) free_tapes(h);
     size_t planes = 0;
     for (auto& c : h->cfg) planes += 9 * plane_of(c);
     h->lam_bytes = round_up(planes * lam_elem, 4096);
@@ -1082,16 +1098,23 @@ extern "C" int lbm_adjoint_begin(lbm_handle* h, const double* seed, int32_t max_
         return m;
     }());
     const size_t nt = h->htiles.size();
-    h->tape_f.assign(max_segment, nullptr);
-    for (int t = 0; t < max_segment; ++t)
-        if (hipMalloc(&h->tape_f[t], h->buf_bytes) != hipSuccess) {
-            free_adjoint(h);
-            FAIL(h, LBM_ENOMEM, "tape of %d steps (%zu bytes each) does not fit", max_segment, h->buf_bytes);
-        }
     auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
-    bool ok = alloc((void**)&h->tape_p, sizeof(PartDev) * (size_t)(max_segment + 1) * std::max(np, 1)) &&
-              alloc((void**)&h->tape_patch, sizeof(double2) * (size_t)max_segment * std::max<long long>(h->cells, 1)) &&
-              alloc(&h->lam[0], 2 * h->lam_bytes) && alloc((void**)&h->dap, sizeof(AdjPart) * ap.size()) &&
+    if (h->tape_f.empty()) {
+        h->tape_f.assign(max_segment, nullptr);
+        for (int t = 0; t < max_segment; ++t)
+            if (hipMalloc(&h->tape_f[t], h->buf_bytes) != hipSuccess) {
+                free_adjoint(h);
+                FAIL(h, LBM_ENOMEM, "tape of %d steps (%zu bytes each) does not fit", max_segment, h->buf_bytes);
+            }
+        if (!alloc((void**)&h->tape_p, sizeof(PartDev) * (size_t)(max_segment + 1) * std::max(np, 1)) ||
+            !alloc((void**)&h->tape_patch, sizeof(double2) * (size_t)max_segment * std::max<long long>(h->cells, 1))) {
+            free_adjoint(h);
+            FAIL(h, LBM_ENOMEM, "allocation of the adjoint tape failed");
+        }
+        h->tape_np = np;
+        h->tape_cells = h->cells;
+    }
+    bool ok = alloc(&h->lam[0], 2 * h->lam_bytes) && alloc((void**)&h->dap, sizeof(AdjPart) * ap.size()) &&
               alloc((void**)&h->dapatch, sizeof(double) * kAdjCell * std::max<long long>(acells, 1)) &&
               alloc((void**)&h->dgmk, sizeof(double) * 5 * nmk) &&
               alloc((void**)&h->dgwall, sizeof(double) * std::max<size_t>(gw, 1)) &&

@@ -413,6 +413,45 @@ def test_adjoint_sweep_equals_segments(storage, overlap):
             assert np.array_equal(x, y)
 
 
+def test_repeated_adjoints_on_one_handle_bitwise():
+    """A second adjoint of the same length on one handle keeps the first's
+    tapes; one of another length allocates new ones.  Every run from the
+    same checkpoints gives bitwise the same gradients and adjoint
+    populations, with the sweep and segment by segment."""
+    from paper_1606_01805_amd import Solver
+
+    cfg = C.couette_config(96, 40, storage=C.STORE_F32)
+    parts = [C.particle(shapes.ellipse(10.0, 2.0, n_markers=40), 30.2, 20.4, 0.7)]
+    s = Solver([(cfg, parts)])
+    for k in range(4):
+        s.checkpoint_save(k)
+        s.step(15, record=False)
+    s.checkpoint_save(4)
+    seed = np.zeros((1, 10))
+    seed[0, :6] = [0.3, 1.0, 0.2, 0.5, -0.4, 1.0]
+
+    def grad(seg, sweep):
+        s.checkpoint_restore(4)
+        s.adjoint_begin(seed, seg)
+        if seg == 15:
+            slots = [3, 2, 1, 0]
+            if sweep:
+                s.adjoint_sweep(slots, 15)
+            else:
+                for k in slots:
+                    s.adjoint_segment(k, 15)
+        else:
+            s.adjoint_segment(0, 60)
+        part, mk, wall = s.adjoint_gradients()
+        return part, mk[0], wall[0], s.adjoint_field(0)
+
+    runs = [grad(15, True), grad(15, True), grad(15, False), grad(60, False), grad(15, True)]
+    s.close()
+    for r in runs[1:]:
+        for x, y in zip(runs[0], r):
+            assert np.array_equal(x, y)
+
+
 def test_adjoint_sweep_rejects_bad_schedules():
     """lbm_adjoint_sweep checks the whole chain of checkpoints before any
     work: an empty list, a slot out of order or a segment longer than the
