@@ -380,21 +380,6 @@ __device__ __forceinline__ void mls_term(const ChanDev& c, const double* S9, con
 // store); a cell is handled by the same thread in every round.  The first
 // round writes the cell (and zeroes fields NZ.. when NZ < kAdjCell), later
 // rounds add to it.
-// acc + v[0][e] + v[1][e] + ... + v[n - 1][e], added in that order, with the
-// LDS reads issued eight at a time instead of one per add.
-__device__ __forceinline__ double ordered_sum8(double acc, const double (*v)[8], int n, int e) {
-    int m = 0;
-    for (; m + 8 <= n; m += 8) {
-        double t[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = v[m + u][e];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += t[u];
-    }
-    for (; m < n; ++m) acc += v[m][e];
-    return acc;
-}
-
 template <int NF, int F0, int W, int NZ>
 __device__ __forceinline__ void deposit_round(double* apatch, int ax0u, int ay0u, int aw, int ah, int ncell,
                                               const int2* anc, const unsigned long long* mask,
@@ -821,7 +806,7 @@ __device__ __forceinline__ void adj_traction_body(const AdjArgs& a, AdjTracLds& 
         // clear the round's anchor bits; running per-particle sums over the
         // markers, ascending
         if (act && k == 0 && ncell <= kAdjMaskCells) s_mask[(s_anc[lo].y - ay0u) * aw + (s_anc[lo].x - ax0u)] = 0ull;
-        if (tid < 7) s_run[tid] = ordered_sum8(s_run[tid], s_pt, min(kAdjRound, nm - r0), tid);
+        if (tid < 7) s_run[tid] = ordered_sum(s_run[tid], &s_pt[0][tid], min(kAdjRound, nm - r0), 8);
         __syncthreads();
     }
     if (tid == 0) {
@@ -1108,7 +1093,7 @@ __device__ __forceinline__ void adj_ibm_body(const AdjArgs& a, AdjIbmLds& sh) {
         }
         __syncthreads();
         if (act && k == 0 && ncell <= kAdjMaskCells) s_mask[(s_anc[lo].y - ay0u) * aw + (s_anc[lo].x - ax0u)] = 0ull;
-        if (tid < 6) s_run[tid] = ordered_sum8(s_run[tid], s_pt, min(kAdjRound, nm - r0), tid);
+        if (tid < 6) s_run[tid] = ordered_sum(s_run[tid], &s_pt[0][tid], min(kAdjRound, nm - r0), 8);
         __syncthreads();
     }
     if (tid == 0) {

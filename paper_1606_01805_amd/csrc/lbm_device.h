@@ -600,6 +600,21 @@ __device__ __forceinline__ void list_insert(int (&L)[N], int& n, int v) {
 
 // Do the boxes [x0, x0 + w) x [y0, y0 + h) and [u0, u0 + p) x [v0, v0 + q)
 // intersect?  Origins may be unwrapped; periodic axes compare modulo n.
+// acc + v[0] + v[stride] + ... + v[(n - 1) * stride], added in that order,
+// with the (LDS) reads issued eight at a time instead of one per add.
+__device__ __forceinline__ double ordered_sum(double acc, const double* v, int n, int stride) {
+    int m = 0;
+    for (; m + 8 <= n; m += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = v[(m + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u];
+    }
+    for (; m < n; ++m) acc += v[m * stride];
+    return acc;
+}
+
 __device__ __forceinline__ bool span_overlap(int x0, int w, int u0, int p, int n, bool per) {
     if (!per) return x0 < u0 + p && u0 < x0 + w;
     if (w >= n || p >= n) return true;

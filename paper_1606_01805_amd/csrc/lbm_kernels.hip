@@ -1061,12 +1061,12 @@ __device__ __forceinline__ void traction_body(const StepArgs& a, const int4 wk) 
             __syncthreads();
             if (tid < 3) {
                 const int n = nm - base < kStage ? nm - base : kStage;
-                for (int j = 0; j < n; ++j) fsum += s_w[3 * j + tid];
+                fsum = ordered_sum(fsum, s_w + tid, n, 3);
             }
             __syncthreads();
         }
     } else if (!skip && tid < 3) {
-        for (int l = 0; l < nm; ++l) fsum += s_t[tid][l];
+        fsum = ordered_sum(fsum, s_t[tid], nm, 1);
     }
     if (tid < 3) sums[tid] = fsum;
     __syncthreads();
