@@ -4,8 +4,10 @@
 // through the moments (Eqs. (6), (7)), the immersed-boundary force and its
 // spreading (Eqs. (8)-(12)), the forced collision (Eqs. (4), (5)), the surface
 // stress with force and moment (Eqs. (13), (14)), BDF2 (Eqs. (15), (16)),
-// streaming and the Zou-He closure (App. A).  Its transpose runs as three
-// kernels per step, in stream order:
+// streaming and the Zou-He closure (App. A).  Its transpose has three
+// stages per step, in this order (as three kernels, or, when no channel holds
+// more than one particle, as adj_particle_kernel + adj_lattice_kernel or as
+// the single adj_step_kernel):
 //
 //   adj_traction  one workgroup per particle: transpose of BDF2 and of the
 //                 probe traction; the field terms (d/d rho and d/d u at the
@@ -15,7 +17,7 @@
 //                 transpose of interpolation and spreading including the
 //                 motion of the MLS weights with the markers; the d/d u* terms
 //                 go into the adjoint patch.
-//   adj_lattice   one workgroup per tile: adjoint streaming (a pull from
+//   adj_lattice   one wave per 64-node chunk of a tile: adjoint streaming (a pull from
 //                 x + e_i), transpose of the collision and of the moments with
 //                 the patch terms added, transpose of the Zou-He closure on
 //                 wall nodes, whose wall-speed derivatives accumulate per node.
