@@ -391,6 +391,47 @@ def test_fused_adjoint_launches_bitwise(storage):
             assert np.array_equal(got[3][j], ref[3][j]), (mode, j)
 
 
+def test_fused_adjoint_launch_forms_edge_cases():
+    """The launch forms of a reversed step stay bitwise equal with a channel
+    that holds no particle (its lattice is updated by the lattice
+    workgroups alone) and on a lattice too large for the whole step to fit
+    the device in one pass (adj_fused = 2 then runs as 1)."""
+    from paper_1606_01805_amd import Solver
+
+    ch0 = C.couette_config(48, 30, tau=0.7, storage=0)
+    ch1 = C.couette_config(40, 24, tau=0.9, storage=0)
+    small = [(ch0, [C.particle(shapes.circle(8.0, n_markers=30), 20.6, 15.2, 0.0, density_ratio=1.1)]),
+             (ch1, [])]
+    big = [(C.couette_config(1024, 300, tau=0.8, storage=0),
+            [C.particle(shapes.ellipse(16.0, 2.0, n_markers=60, mode="param"), 500.3, 150.6, 0.2)])]
+    for chans, T in ((small, 10), (big, 4)):
+        npart = sum(len(p) for _, p in chans)
+        seeds = np.zeros((npart, 10))
+        seeds[:, :6] = np.random.default_rng(41).standard_normal((npart, 6))
+
+        def run(mode):
+            s = Solver(chans, storage=C.STORE_F32, tuning=dict(adj_fused=mode))
+            s.checkpoint_save(0)
+            s.step(T, record=False)
+            s.adjoint_begin(seeds, T)
+            s.adjoint_segment(0, T)
+            part, mk, wall = s.adjoint_gradients()
+            lam = [s.adjoint_field(ci) for ci in range(len(chans))]
+            s.close()
+            return part, mk, wall, lam
+
+        ref = run(0)
+        assert np.any(ref[0] != 0.0)
+        for mode in (1, 2):
+            got = run(mode)
+            assert np.array_equal(got[0], ref[0]), mode
+            for j in range(len(ref[1])):
+                assert np.array_equal(got[1][j], ref[1][j]), mode
+            for ci in range(len(chans)):
+                assert np.array_equal(got[2][ci], ref[2][ci]), mode
+                assert np.array_equal(got[3][ci], ref[3][ci]), mode
+
+
 @pytest.mark.parametrize("storage,overlap", [(C.STORE_F32, 0), (C.STORE_F32, 1), (C.STORE_F64, 0)])
 def test_adjoint_sweep_equals_segments(storage, overlap):
     """lbm_adjoint_sweep (the next segment recomputed on a second stream
