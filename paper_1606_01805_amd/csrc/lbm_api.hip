@@ -104,6 +104,7 @@ struct lbm_handle {
     double* dds = nullptr;
     double2* dpatch = nullptr;
     int4* dwork = nullptr;         // particle-kernel workgroups (particle, round, channel, 0)
+    int4 hwork0 = {0, 0, 0, 0};    // its first entry
     int nwork = 0;
     int2* dpsum = nullptr;         // partial-patch sum chunks (particle, first cell)
     int npsum = 0;
@@ -275,6 +276,7 @@ static StepArgs make_args(lbm_handle* h, int cur, int parity = -1) {
     a.patch = h->dpatch;
     a.work = h->dwork;
     a.nwork = h->nwork;
+    a.work0 = h->hwork0;
     a.psum = h->dpsum;
     a.npsum = h->npsum;
     a.sum_partials = 1;
@@ -584,6 +586,7 @@ static int finalize(lbm_handle* h) {
         }
     }
     h->nwork = (int)work.size();
+    h->hwork0 = work.empty() ? make_int4(0, 0, 0, 0) : work[0];
     h->npsum = (int)psum.size();
     HIPCHK(h, hipMalloc(&h->dpartial, sizeof(double2) * std::max<long long>(pcells, 1)));
     HIPCHK(h, hipMalloc(&h->dwork, sizeof(int4) * std::max<size_t>(work.size(), 1)));

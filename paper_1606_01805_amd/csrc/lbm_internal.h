@@ -93,6 +93,8 @@ struct StepArgs {
                              // round << 16, channel, first marker of the round in the
                              // marker arrays); see work_entry
     int nwork;
+    int4 work0;              // work[0], carried in the arguments: the first workgroup's
+                             // particle loads need no dependent read of the table
     int* pcount;             // [nparts] finished surface-stress workgroups; 0 between launches
     double2* partial;        // per-round partial force patches of particles of several rounds
     int sum_partials;        // 1: readers of the patch of a particle of several rounds add

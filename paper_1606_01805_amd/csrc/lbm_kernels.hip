@@ -147,6 +147,18 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// Work entry of particle-kernel workgroup b.  The first comes with the
+// kernel arguments, so that its particle loads need no dependent read.
+__device__ __forceinline__ int4 work_of(const StepArgs& a, int b) {
+    int4 w;
+    if (b == 0) {
+        w = a.work0;
+    } else {
+        w = a.work[b];
+    }
+    return w;
+}
+
 // Two of the particle kernels' 9-wave workgroups share a CU only at six or
 // more waves per SIMD (a workgroup places three of its waves on one SIMD;
 // measured: at five waves per SIMD one workgroup runs per CU), and only
@@ -166,7 +178,7 @@ void ibm_force_kernel(StepArgs a) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0 && tid == 0) atomicAdd((unsigned long long*)a.dstep, 1ull);
     if ((int)blockIdx.x >= a.nwork) return;
-    const int4 wk = a.work[blockIdx.x];
+    const int4 wk = work_of(a, (int)blockIdx.x);
     const int pid = wk.x, rnd = work_round(wk), nact = work_count(wk);
     PartDev* P = a.parts + pid;
     const ChanDev c = load_chan(a.chan + wk.z);  // issued beside the particle's loads
@@ -1133,7 +1145,7 @@ template <int ST, bool PAIR>
 __global__ __launch_bounds__(kIbmThreads) __attribute__((amdgpu_waves_per_eu(PAIR ? 6 : 1)))
 void traction_kernel(StepArgs a) {
     if ((int)blockIdx.x < a.nwork) {
-        const int4 wk = a.work[blockIdx.x];
+        const int4 wk = work_of(a, (int)blockIdx.x);
         traction_body<ST>(a, wk);
     }
 }
@@ -1151,7 +1163,7 @@ __global__ __launch_bounds__(kIbmThreads) void lattice_traction_kernel(StepArgs 
     const int j = (int)blockIdx.x - tb;
     if (j < 0) {
         if ((int)blockIdx.x < a.nwork) {
-            const int4 wk = a.work[blockIdx.x];
+            const int4 wk = work_of(a, (int)blockIdx.x);
             traction_body<ST>(a, wk);
         }
         return;
@@ -1178,7 +1190,7 @@ void lattice_traction_vkernel(StepArgs a, int tb) {
     const int j = (int)blockIdx.x - tb;
     if (j < 0) {
         if ((int)blockIdx.x < a.nwork) {
-            const int4 wk = a.work[blockIdx.x];
+            const int4 wk = work_of(a, (int)blockIdx.x);
             traction_body<ST, 256>(a, wk);
         }
         return;
